@@ -1,0 +1,164 @@
+"""Benchmark of the colour-gradient D3Q19 step on one MI355X.
+
+Workload: the 256^3 periodic emulsion (radii U[6,12], RSA to volume fraction
+0.30, tau = 0.8, A = 0.005, beta = 0.7, near-contact strength 0.02 over 2
+sites), seeded and synthetic.  A step is one full update of every site.
+
+Prints ONE JSON line: MLUPS of the FP32-storage stepper (the headline value),
+the same workload in the 16-bit storage forms, the roofline figures of the
+dominant kernel (algorithmic bytes per launch over its HIP-event duration),
+and the FP64 CPU oracle timed on this host as the CPU baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per site update: 2 components x 19 populations x (read + write)
+ALGO_BYTES = {0: 2 * 19 * 2 * 8, 1: 2 * 19 * 2 * 4, 2: 2 * 19 * 2 * 2, 3: 2 * 19 * 2 * 2}
+STORE_NAME = {0: "f64", 1: "f32", 2: "f16", 3: "bf16"}
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def gpu_variant(w, storage, steps, warmup, stream, kernel=0):
+    import torch
+    from paper_2005_12764_amd import lb
+
+    p = dict(w.params, storage=storage, kernel=kernel)
+    L = lb.Lattice(p, stream=stream)
+    try:
+        L.init(w.rho_r, w.rho_b)
+        L.step(warmup)
+        torch.cuda.synchronize()
+        start = torch.cuda.Event(enable_timing=True)
+        stop = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        start.record(stream)
+        L.step(steps)
+        stop.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = start.elapsed_time(stop) / steps
+        # per-pass durations with HIP events on the lattice's stream
+        k_ms = lb.lb_step_timed(L.h, min(steps, 50))
+        tot = L.totals()
+        ok = tot[6].sum() == 0 and np.isfinite(tot[:5].sum())
+        return dict(ms_per_step=ms, wall_s=wall, kernel=L.kernel, pass_ms=k_ms, finite=bool(ok))
+    finally:
+        L.close()
+
+
+def cpu_baseline(w, steps):
+    from oracle import oracle as O
+    from tests.helpers import oracle_params
+
+    prm = oracle_params(dict(w.params, storage=0))
+    f = O.init(prm, w.rho_r, w.rho_b)
+    t0 = time.perf_counter()
+    O.step(prm, f, steps)
+    dt = time.perf_counter() - t0
+    return dict(value=w.sites * steps / dt / 1e6, unit="MLUPS", cores=O.threads(), kind="oracle",
+                sample="%d step(s) of the full %s lattice (%d sites), FP64, OpenMP over sites"
+                       % (steps, "x".join(str(s) for s in w.shape[::-1]), w.sites),
+                seconds=dt)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=256, help="lattice side of the emulsion")
+    ap.add_argument("--variants", default="f32,f16,bf16")
+    ap.add_argument("--kernel", type=int, default=0, help="0 auto, 1 two-pass, 2 fused")
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the domain decomposition is a design note); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2005_12764_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    w = W.periodic_emulsion(seed=0, n=args.n, storage=W.F32)
+    log("workload %s: %d sites, %d droplets, phi_v %.3f (%.1fs)"
+        % (w.name, w.sites, w.info["n_droplets"], w.info["rsa_phi_v"], time.perf_counter() - t0))
+
+    codes = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
+    results = {}
+    for name in args.variants.split(","):
+        st = codes[name]
+        r = gpu_variant(w, st, args.steps, args.warmup, stream, args.kernel)
+        r["mlups"] = w.sites / (r["ms_per_step"] * 1e-3) / 1e6
+        r["algo_gbs"] = r["mlups"] * 1e6 * ALGO_BYTES[st] / 1e9
+        results[name] = r
+        log("%s: %.3f ms/step, %.0f MLUPS, %.0f GB/s algorithmic, passes %s"
+            % (name, r["ms_per_step"], r["mlups"], r["algo_gbs"], r["pass_ms"]))
+
+    head = results.get("f32") or next(iter(results.values()))
+    head_name = "f32" if "f32" in results else next(iter(results))
+    st = codes[head_name]
+    # dominant kernel: the collide-and-stream (or fused) pass
+    dom_ms = head["pass_ms"][1]
+    achieved = ALGO_BYTES[st] * w.sites / (dom_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "collide_kernel" if head["kernel"] == 1 else "fused_kernel",
+            "algo_bytes_per_site": ALGO_BYTES[st], "sites_per_launch": w.sites,
+            "kernel_ms": round(dom_ms, 4)}
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(w, args.cpu_steps)
+        log("cpu oracle: %.2f MLUPS on %d threads (%.1fs)" % (cpu["value"], cpu["cores"], cpu["seconds"]))
+
+    out = {
+        "metric": "MLUPS and HBM GB/s (% of peak), FP16-store vs FP32; p50/p99 sweep-job latency",
+        "value": round(head["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "periodic emulsion %d^3, phi_v 0.30, R U[6,12], tau 0.8, A 0.005, "
+                               "beta 0.7, near-contact 0.02 over 2 sites" % args.n,
+                   "sites": w.sites, "storage": head_name,
+                   "kernel": "two-pass" if head["kernel"] == 1 else "fused",
+                   "parallelism": "single GPU"},
+        "hbm_gbs_algorithmic": round(head["algo_gbs"], 1),
+        "hbm_frac_algorithmic": round(head["algo_gbs"] / HBM_PEAK_GBS, 4),
+        "variants": {k: {"mlups": round(v["mlups"], 1), "ms_per_step": round(v["ms_per_step"], 4),
+                         "algo_gbs": round(v["algo_gbs"], 1),
+                         "pass_ms": [round(x, 4) for x in v["pass_ms"]],
+                         "finite": v["finite"]} for k, v in results.items()},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

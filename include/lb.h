@@ -1,0 +1,167 @@
+/*
+ * lb.h -- C ABI of liblb.so: the two-component colour-gradient lattice
+ * Boltzmann update on a D3Q19 lattice, for AMD Instinct MI355X (gfx950).
+ *
+ * What one step computes (arXiv 2005.12764, "Towards Exascale Design of Soft
+ * Mesoscale Materials"):
+ *   - two fluid components r and b, each with its own 19 populations
+ *     (Sec. 2.1, eq:twobgk), relaxed by BGK toward the second-order equilibrium
+ *     (Sec. 2, eq:equil) with one mixture rate w_eff taken from the
+ *     density-weighted harmonic mean of the component viscosities
+ *     nu_k = (tau_k - 1/2)/3 (Sec. 2.1, eq:twobgk with Sec. 2, eq:eq3);
+ *   - a force density F acting through the exact-difference source
+ *     S_i = f^eq(rho_k, u + F/rho) - f^eq(rho_k, u) (Sec. 2.1, eq:edm):
+ *     a uniform body force plus the near-contact repulsion
+ *     F_rep = -A_h[h] n delta_I of Sec. 4 (F_rep equation);
+ *   - the colour-gradient surface-tension perturbation and recolouring of
+ *     colour-gradient models (the paper uses them without writing them out);
+ *   - streaming, an exact memory shift (Sec. 2), with periodic axes or halfway
+ *     bounce-back walls.
+ * The readings of the paper that the library takes where the text is silent
+ * or garbled (sign of w_eff, force split, the discrete near-contact probe,
+ * gradient at walls) are documented with the design notes of the repository.
+ *
+ * Conventions
+ *   - Fields are C-order [z][y][x], x fastest.  Vector fields are SoA
+ *     [3][z][y][x].  Populations exchanged through lb_get_state/lb_set_state
+ *     are [2][19][z][y][x]: component (0 red, 1 blue), direction, site, in the
+ *     post-streaming (pre-collision) state f_i(x, t).
+ *   - Direction order: 0 rest; 1..6 = +x,-x,+y,-y,+z,-z; 7..18 = (1,1,0),
+ *     (-1,-1,0), (1,-1,0), (-1,1,0), (1,0,1), (-1,0,-1), (1,0,-1), (-1,0,1),
+ *     (0,1,1), (0,-1,-1), (0,1,-1), (0,-1,1).  Weights 1/3, 1/18, 1/36.
+ *   - "on_device" = 1: the pointer is device memory of the handle's device
+ *     (e.g. a torch tensor's data_ptr()); 0: host memory.
+ *   - Return value: LB_OK (0) or a negative LB_E* code; lb_last_error() gives
+ *     a message for the calling thread.  A failed call leaves the state as it
+ *     was.  No C++ exception crosses this interface.
+ *   - Stream semantics: every call is ordered on the handle's HIP stream.
+ *     lb_step and device-pointer transfers do not block the host; calls that
+ *     read into host memory (or fill `totals`) synchronise the stream.
+ *   - Thread safety: one handle must not be used from two threads at once.
+ */
+#ifndef LB_H
+#define LB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LB_OK 0
+#define LB_EINVAL (-1)  /* bad argument or parameter */
+#define LB_ENOMEM (-2)  /* device allocation failed */
+#define LB_EDEVICE (-3) /* HIP runtime error (launch, copy, no device) */
+#define LB_ESTATE (-4)  /* call out of order, e.g. stepping before init */
+
+/* Population storage. */
+#define LB_STORE_F64 0  /* raw FP64 populations, 2 x 19 x 8 B per site */
+#define LB_STORE_F32 1  /* raw FP32 populations, 2 x 19 x 4 B per site */
+#define LB_STORE_F16 2  /* 16-bit moment-split: per site FP32 rho, u, red fraction and
+                           recolouring vector (32 B) + per direction the deviation of
+                           the total population from its local equilibrium in fp16,
+                           scaled by 2^scale_log2 (38 B); computes in FP32 */
+#define LB_STORE_BF16 3 /* as LB_STORE_F16 with bf16 deviations (no scale) */
+
+/* Kernel selection for lb_step. */
+#define LB_KERNEL_AUTO 0    /* fused when the lattice allows it, else two-pass */
+#define LB_KERNEL_TWOPASS 1 /* phase-field pass, then collide-and-stream pass */
+#define LB_KERNEL_FUSED 2   /* single pass: z-marching tiles, phase field in LDS */
+
+/* Element type of caller fields. */
+#define LB_DTYPE_F64 0
+#define LB_DTYPE_F32 1
+
+/* Largest near-contact probe range K the kernels support. */
+#define LB_MAX_NC_RANGE 4
+
+typedef struct lb_t lb_t; /* opaque, owned by the library */
+
+typedef struct {
+    int32_t nx, ny, nz;     /* lattice size, >= 1 each; every site is fluid */
+    int32_t bc[3];          /* per axis x,y,z: 0 periodic, 1 halfway bounce-back walls at both
+                               faces (walls at -1/2 and n-1/2) */
+    int32_t storage;        /* LB_STORE_* */
+    int32_t kernel;         /* LB_KERNEL_* */
+    double tau_r, tau_b;    /* relaxation times of the components, > 1/2 (eq:eq3) */
+    double A;               /* surface-tension perturbation amplitude, >= 0 */
+    double beta;            /* recolouring segregation parameter, in [0, 1] */
+    double nc_strength;     /* near-contact strength A of Sec. 4 (0 = off) */
+    int32_t nc_range;       /* probe range K in sites, 0..LB_MAX_NC_RANGE */
+    int32_t scale_log2;     /* LB_STORE_F16 scale exponent; 0 = default (16) */
+    double nc_hmin;         /* h_min: full strength for h <= h_min, h^-3 decay beyond */
+    double body_force[3];   /* uniform force density */
+    double eps_g;           /* |G| at or below which the interface normal is zero;
+                               <= 0 selects 1e-12 (F64) or 1e-6 (other storage) */
+    double g_iface;         /* |G| threshold of interface sites for the near-contact
+                               probe; <= 0 selects 0.05 */
+} lb_params;
+
+/* Create a lattice on the current HIP device.  Allocates the two population
+ * buffers (ping-pong) and the phase-field scratch; the library owns them.
+ * hip_stream: a hipStream_t to order all work on, or NULL for the default
+ * stream.  On success *out is a new handle; nothing is allocated on failure.
+ * LB_EINVAL: size < 1, tau <= 1/2, nc_range outside 0..LB_MAX_NC_RANGE,
+ * unknown storage or kernel, lattice too large for 32-bit site indices. */
+int lb_create(const lb_params* params, void* hip_stream, lb_t** out);
+
+/* Set the initial state f^k_i = f^eq_i(rho_k, u) (Sec. 2, eq:equil).
+ * rho_r, rho_b: N = nx*ny*nz component densities; u: 3N velocity (SoA) or
+ * NULL for zero.  dtype: LB_DTYPE_*.  The densities must be >= 0 with
+ * rho_r + rho_b > 0 (not checked on device pointers).  Resets the step count. */
+int lb_init_fields(lb_t* h, const void* rho_r, const void* rho_b, const void* u, int32_t dtype,
+                   int32_t on_device);
+
+/* Enqueue n >= 0 full steps (collide, then stream). */
+int lb_step(lb_t* h, int32_t n);
+
+/* As lb_step, timing every pass with HIP events on the handle's stream;
+ * blocks until the n steps are done.  kernel_ms (host, 3 values) receives the
+ * mean milliseconds per step of: [0] the phase-field pass (0 for the fused
+ * kernel), [1] the collide-and-stream (or fused) pass, [2] the whole step. */
+int lb_step_timed(lb_t* h, int32_t n, double kernel_ms[3]);
+
+/* Moments of the current state (Sec. 2, eq:eq2): rho_r, rho_b (N each) and the
+ * bare momentum mom = sum_i (f^r_i + f^b_i) c_i (3N, SoA).  Any of the three may
+ * be NULL.  The physical velocity is (mom + F/2)/rho with F the force density
+ * of the last step.  totals (host, may be NULL) receives 7 compensated FP64
+ * (sum, correction) pairs, in order: total red mass, total blue mass, momentum
+ * x, y, z, kinetic energy sum |mom|^2/(2 rho), and the number of sites with a
+ * non-finite or non-positive density; each total is sum + correction. */
+int lb_moments(lb_t* h, void* rho_r, void* rho_b, void* mom, int32_t dtype, int32_t on_device,
+               double totals[14]);
+
+/* Export the populations f_i(x, t) (post-streaming state) as [2][19][N]
+ * values of the given dtype.  For 16-bit storage these are the decoded values. */
+int lb_get_state(lb_t* h, void* f, int32_t dtype, int32_t on_device);
+
+/* Import populations in the layout of lb_get_state (16-bit storage re-encodes
+ * them).  Keeps the step count. */
+int lb_set_state(lb_t* h, const void* f, int32_t dtype, int32_t on_device);
+
+/* Raw storage of the current state (checkpoint): lb_state_bytes gives the
+ * size; lb_save_raw/lb_load_raw copy it out/in unchanged (bitwise resume). */
+int64_t lb_state_bytes(const lb_t* h);
+int lb_save_raw(lb_t* h, void* dst, int32_t on_device);
+int lb_load_raw(lb_t* h, const void* src, int32_t on_device);
+
+/* Steps taken since lb_init_fields. */
+int64_t lb_step_count(const lb_t* h);
+
+/* Kernel lb_step actually uses (LB_KERNEL_TWOPASS or LB_KERNEL_FUSED). */
+int lb_kernel_in_use(const lb_t* h);
+
+/* Release every buffer of the handle (after finishing its queued work). */
+int lb_destroy(lb_t* h);
+
+/* Message of the calling thread's last failure ("" if none). */
+const char* lb_last_error(void);
+
+/* Bytes of device memory a lattice with these parameters holds. */
+int64_t lb_footprint_bytes(const lb_params* params);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LB_H */

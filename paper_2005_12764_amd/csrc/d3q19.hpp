@@ -1,0 +1,152 @@
+// d3q19.hpp -- device-side lattice tables and the local colour-gradient
+// collision for gfx950.  Device code only; every loop over directions is
+// fully unrolled so the lattice vectors and weights fold into immediates.
+//
+// Method (arXiv 2005.12764):
+//   equilibrium w_i rho (1 + u_i + q_i)                     Sec. 2, eq:equil
+//   BGK with mixture rate w_eff and harmonic nu_bar          Sec. 2.1, eq:twobgk
+//   exact-difference source f^eq(u + F/rho) - f^eq(u)        Sec. 2.1, eq:edm
+//   near-contact force F_rep = -A_h[h] n delta_I             Sec. 4
+// plus the colour-gradient perturbation (Reis-Phillips, D3Q19 coefficients
+// of Liu-Valocchi-Kang) and Latva-Kokko-Rothman recolouring, which the paper
+// uses but does not write out.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+constexpr int Q = 19;
+
+// Direction order: rest, +x,-x,+y,-y,+z,-z, then the 12 face diagonals in
+// opposite pairs.  This order is part of the library's state layout.
+struct Lattice {
+    static constexpr int cx[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+    static constexpr int cy[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+    static constexpr int cz[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+    static constexpr int opp[Q] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+    static constexpr int len2(int i) { return cx[i] * cx[i] + cy[i] * cy[i] + cz[i] * cz[i]; }
+};
+
+template <typename R>
+__host__ __device__ constexpr R weight(int i) {
+    return Lattice::len2(i) == 0 ? R(1) / R(3) : (Lattice::len2(i) == 1 ? R(1) / R(18) : R(1) / R(36));
+}
+// B_i of the perturbation operator: -1/3, 1/18, 1/36 by shell.
+template <typename R>
+__host__ __device__ constexpr R bpert(int i) {
+    return Lattice::len2(i) == 0 ? -R(1) / R(3) : (Lattice::len2(i) == 1 ? R(1) / R(18) : R(1) / R(36));
+}
+// 1/|c_i| (0 for the rest vector, whose recolouring term vanishes).
+template <typename R>
+__host__ __device__ constexpr R inv_clen(int i) {
+    return Lattice::len2(i) == 0 ? R(0)
+                                 : (Lattice::len2(i) == 1 ? R(1) : R(0.70710678118654752440084436210485));
+}
+
+// Per-lattice constants in the compute type, prepared on the host.
+template <typename R>
+struct Coeffs {
+    R inv_nu_r, inv_nu_b;  // 1 / nu_k, nu_k = (tau_k - 1/2)/3
+    R half_A;              // A/2 of the perturbation
+    R beta;
+    R eps_g;               // |G| at or below which n = 0
+    R g_iface;             // interface threshold of the near-contact probe
+    R nc_strength, nc_hmin;
+    R fx, fy, fz;          // body force density
+    int nc_range;          // 0 = near-contact off
+};
+
+// Outputs of one site's collision that the 16-bit storage keeps per site.
+template <typename R>
+struct SiteTotals {
+    R rho, ux, uy, uz;     // post-collision density and velocity (j + F)/rho
+    R xr;                  // red fraction rho_r/rho
+    R vx, vy, vz;          // recolouring vector beta (rho_r rho_b/rho) G/|G|
+};
+
+// Local collision of one site.  fr/fb hold the pulled (post-streaming)
+// populations on entry and the post-collision, recoloured populations on exit.
+// (gx,gy,gz) is the colour gradient at the site, (Fx,Fy,Fz) the total force.
+template <typename R>
+__device__ __forceinline__ void collide(R (&fr)[Q], R (&fb)[Q], R gx, R gy, R gz, R Fx, R Fy,
+                                        R Fz, const Coeffs<R>& c, SiteTotals<R>* tot = nullptr) {
+    using L = Lattice;
+    R rr = R(0), rb = R(0), jx = R(0), jy = R(0), jz = R(0);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        rr += fr[i];
+        rb += fb[i];
+        const R t = fr[i] + fb[i];
+        if (L::cx[i]) jx += L::cx[i] > 0 ? t : -t;
+        if (L::cy[i]) jy += L::cy[i] > 0 ? t : -t;
+        if (L::cz[i]) jz += L::cz[i] > 0 ? t : -t;
+    }
+    const R rho = rr + rb;
+    const R inv_rho = R(1) / rho;
+    const R ux = jx * inv_rho, uy = jy * inv_rho, uz = jz * inv_rho;
+    // exact-difference velocity shift: F^k/rho_k with F^k = (rho_k/rho) F
+    const R vx = ux + Fx * inv_rho, vy = uy + Fy * inv_rho, vz = uz + Fz * inv_rho;
+    const R xr = rr * inv_rho, xb = rb * inv_rho;
+    // mixture relaxation: 1/nu_bar = x_r/nu_r + x_b/nu_b, w = 2 cs2/(2 nu_bar + cs2)
+    const R nubar = R(1) / (xr * c.inv_nu_r + xb * c.inv_nu_b);
+    const R omega = R(2) / (R(6) * nubar + R(1));
+    const R uu = ux * ux + uy * uy + uz * uz;
+    const R vv = vx * vx + vy * vy + vz * vz;
+
+    const R g2 = gx * gx + gy * gy + gz * gz;
+    const R gm = sqrt(g2);
+    const bool has_n = gm > c.eps_g;
+    const R inv_gm = has_n ? R(1) / gm : R(0);
+    // perturbation amplitude (A/2)|G| and recolouring strength beta rho_r rho_b / rho
+    const R pa = has_n ? c.half_A * gm : R(0);
+    const R seg = has_n ? c.beta * rr * rb * inv_rho : R(0);
+    const R nx = gx * inv_gm, ny = gy * inv_gm, nz = gz * inv_gm;
+
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const R w = weight<R>(i);
+        const R cu = R(L::cx[i]) * ux + R(L::cy[i]) * uy + R(L::cz[i]) * uz;
+        const R cv = R(L::cx[i]) * vx + R(L::cy[i]) * vy + R(L::cz[i]) * vz;
+        const R e = w * (R(1) + R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu);   // f^eq/rho_k at u
+        const R es = w * (R(1) + R(3) * cv + R(4.5) * cv * cv - R(1.5) * vv);  // at u + F/rho
+        const R pr = fr[i] - omega * (fr[i] - rr * e) + rr * (es - e);
+        const R pb = fb[i] - omega * (fb[i] - rb * e) + rb * (es - e);
+        const R cn = R(L::cx[i]) * nx + R(L::cy[i]) * ny + R(L::cz[i]) * nz;   // c_i . n
+        const R fs = pr + pb + pa * (w * cn * cn - bpert<R>(i));
+        const R rec = seg * w * cn * inv_clen<R>(i);
+        fr[i] = xr * fs + rec;
+        fb[i] = xb * fs - rec;
+    }
+    if (tot) {
+        tot->rho = rho;
+        tot->ux = vx;  // (j + F)/rho
+        tot->uy = vy;
+        tot->uz = vz;
+        tot->xr = xr;
+        tot->vx = seg * nx;
+        tot->vy = seg * ny;
+        tot->vz = seg * nz;
+    }
+}
+
+// Equilibrium divided by the density, for the 16-bit codec and init.
+template <typename R>
+__device__ __forceinline__ R feq_unit(int i, R ux, R uy, R uz) {
+    using L = Lattice;
+    const R cu = R(L::cx[i]) * ux + R(L::cy[i]) * uy + R(L::cz[i]) * uz;
+    const R uu = ux * ux + uy * uy + uz * uz;
+    return weight<R>(i) * (R(1) + R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu);
+}
+
+// Near-contact amplitude A_h(h): full strength up to h_min, h^-3 beyond,
+// zero outside 1..K.
+template <typename R>
+__device__ __forceinline__ R nc_amplitude(int h, const Coeffs<R>& c) {
+    if (h < 1 || h > c.nc_range) return R(0);
+    if (R(h) <= c.nc_hmin) return c.nc_strength;
+    const R r = c.nc_hmin / R(h);
+    return c.nc_strength * r * r * r;
+}
+
+}  // namespace lbm

@@ -1,0 +1,453 @@
+// lb_api.hip -- host side of liblb.so: handle, parameter validation, buffer
+// ownership, kernel dispatch and the C ABI declared in include/lb.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "lb.h"
+#include "lb_internal.hpp"
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+int check_hip(hipError_t e, const char* what) {
+    if (e == hipSuccess) return LB_OK;
+    return fail(e == hipErrorOutOfMemory ? LB_ENOMEM : LB_EDEVICE,
+                std::string(what) + ": " + hipGetErrorString(e));
+}
+
+}  // namespace
+
+namespace lbm {
+
+int set_error(int code, const char* msg) { return fail(code, msg); }
+
+int validate_params(const lb_params* p, std::string& why) {
+    if (!p) return why = "params is NULL", LB_EINVAL;
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1) return why = "lattice sizes must be >= 1", LB_EINVAL;
+    const double n = double(p->nx) * double(p->ny) * double(p->nz);
+    if (n * Q > 9.0e18 || n >= 2147483647.0) return why = "lattice too large (sites must fit in 31 bits)", LB_EINVAL;
+    for (int a = 0; a < 3; ++a)
+        if (p->bc[a] != 0 && p->bc[a] != 1) return why = "bc must be 0 (periodic) or 1 (walls)", LB_EINVAL;
+    if (p->storage < LB_STORE_F64 || p->storage > LB_STORE_BF16) return why = "unknown storage", LB_EINVAL;
+    if (p->kernel < LB_KERNEL_AUTO || p->kernel > LB_KERNEL_FUSED) return why = "unknown kernel", LB_EINVAL;
+    if (!(p->tau_r > 0.5) || !(p->tau_b > 0.5) || !std::isfinite(p->tau_r) || !std::isfinite(p->tau_b))
+        return why = "tau_r and tau_b must be finite and > 1/2", LB_EINVAL;
+    if (!(p->A >= 0.0) || !std::isfinite(p->A)) return why = "A must be finite and >= 0", LB_EINVAL;
+    if (!(p->beta >= 0.0 && p->beta <= 1.0)) return why = "beta must lie in [0, 1]", LB_EINVAL;
+    if (!std::isfinite(p->nc_strength) || p->nc_strength < 0.0) return why = "nc_strength must be finite and >= 0", LB_EINVAL;
+    if (p->nc_range < 0 || p->nc_range > LB_MAX_NC_RANGE) return why = "nc_range outside 0..LB_MAX_NC_RANGE", LB_EINVAL;
+    if (!(p->nc_hmin > 0.0) && p->nc_range > 0 && p->nc_strength > 0) return why = "nc_hmin must be > 0", LB_EINVAL;
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(p->body_force[a])) return why = "body_force must be finite", LB_EINVAL;
+    if (p->scale_log2 < 0 || p->scale_log2 > 24) return why = "scale_log2 outside 0..24", LB_EINVAL;
+    if (!std::isfinite(p->eps_g) || !std::isfinite(p->g_iface)) return why = "eps_g, g_iface must be finite", LB_EINVAL;
+    return LB_OK;
+}
+
+template <typename R>
+Coeffs<R> make_coeffs(const lb_params& p) {
+    Coeffs<R> c;
+    const double nu_r = (p.tau_r - 0.5) / 3.0, nu_b = (p.tau_b - 0.5) / 3.0;
+    c.inv_nu_r = R(1.0 / nu_r);
+    c.inv_nu_b = R(1.0 / nu_b);
+    c.half_A = R(0.5 * p.A);
+    c.beta = R(p.beta);
+    c.eps_g = R(p.eps_g > 0 ? p.eps_g : (p.storage == LB_STORE_F64 ? 1e-12 : 1e-6));
+    c.g_iface = R(p.g_iface > 0 ? p.g_iface : 0.05);
+    c.nc_strength = R(p.nc_strength);
+    c.nc_hmin = R(p.nc_hmin);
+    c.fx = R(p.body_force[0]);
+    c.fy = R(p.body_force[1]);
+    c.fz = R(p.body_force[2]);
+    c.nc_range = (p.nc_strength > 0.0) ? p.nc_range : 0;
+    return c;
+}
+template Coeffs<double> make_coeffs<double>(const lb_params&);
+template Coeffs<float> make_coeffs<float>(const lb_params&);
+
+Geom make_geom(const lb_params& p) {
+    Geom g;
+    g.nx = p.nx;
+    g.ny = p.ny;
+    g.nz = p.nz;
+    g.wx = p.bc[0];
+    g.wy = p.bc[1];
+    g.wz = p.bc[2];
+    g.nxy = p.nx * p.ny;
+    g.N = p.nx * p.ny * p.nz;
+    return g;
+}
+
+size_t pop_bytes(int storage, size_t N) {
+    switch (storage) {
+        case LB_STORE_F64: return 2 * Q * N * sizeof(double);
+        case LB_STORE_F32: return 2 * Q * N * sizeof(float);
+        default: return 8 * N * sizeof(float) + Q * N * 2;
+    }
+}
+
+}  // namespace lbm
+
+// ---------------------------------------------------------------------------
+// Handle
+// ---------------------------------------------------------------------------
+struct lb_t {
+    lb_params p;
+    Geom g;
+    hipStream_t stream;
+    int device;
+    void* buf[2];      // post-collision populations, ping-pong
+    void* pending;     // raw FP32 state of a 16-bit lattice before its first step
+    void* phi;         // phase field (double for F64, float otherwise)
+    Neu* partial;      // reduction partials
+    double* dtot;      // device totals [14]
+    int cur;           // buffer holding the current state
+    int64_t steps;
+    bool initialised;
+    int kernel;        // LB_KERNEL_TWOPASS or LB_KERNEL_FUSED
+    Coeffs<double> cd;
+    Coeffs<float> cf;
+};
+
+namespace {
+
+lbm::LatticeView view_of(lb_t* h) {
+    lbm::LatticeView v;
+    v.p = &h->p;
+    v.g = h->g;
+    v.stream = h->stream;
+    v.cur = h->buf[h->cur];
+    v.nxt = h->buf[h->cur ^ 1];
+    v.pending = h->pending;
+    v.phi = h->phi;
+    v.cd = h->cd;
+    v.cf = h->cf;
+    return v;
+}
+
+void release(lb_t* h) {
+    if (!h) return;
+    if (h->buf[0]) (void)hipFree(h->buf[0]);
+    if (h->buf[1]) (void)hipFree(h->buf[1]);
+    if (h->pending) (void)hipFree(h->pending);
+    if (h->phi) (void)hipFree(h->phi);
+    if (h->partial) (void)hipFree(h->partial);
+    if (h->dtot) (void)hipFree(h->dtot);
+    delete h;
+}
+
+int copy_in(const void* src, int on_device, size_t bytes, void** dev_out, void* scratch, hipStream_t st) {
+    if (on_device) {
+        *dev_out = const_cast<void*>(src);
+        return LB_OK;
+    }
+    int rc = check_hip(hipMemcpyAsync(scratch, src, bytes, hipMemcpyHostToDevice, st), "hipMemcpyAsync H2D");
+    *dev_out = scratch;
+    return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lb_last_error(void) { return g_err.c_str(); }
+
+int64_t lb_footprint_bytes(const lb_params* p) {
+    std::string why;
+    if (validate_params(p, why) != LB_OK) return -1;
+    const size_t N = size_t(p->nx) * p->ny * p->nz;
+    size_t b = 2 * pop_bytes(p->storage, N) + N * (p->storage == LB_STORE_F64 ? 8 : 4);
+    return (int64_t)b;
+}
+
+int lb_create(const lb_params* params, void* hip_stream, lb_t** out) {
+    if (!out) return fail(LB_EINVAL, "out is NULL");
+    *out = nullptr;
+    std::string why;
+    if (validate_params(params, why) != LB_OK) return fail(LB_EINVAL, why);
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(LB_EDEVICE, "no HIP device");
+    lb_t* h = new (std::nothrow) lb_t();
+    if (!h) return fail(LB_ENOMEM, "host allocation failed");
+    h->p = *params;
+    if (h->p.scale_log2 == 0) h->p.scale_log2 = 16;
+    h->g = make_geom(h->p);
+    h->stream = (hipStream_t)hip_stream;
+    (void)hipGetDevice(&h->device);
+    h->cd = make_coeffs<double>(h->p);
+    h->cf = make_coeffs<float>(h->p);
+    h->kernel = choose_kernel(h->p);
+    const size_t N = (size_t)h->g.N;
+    const size_t pb = pop_bytes(h->p.storage, N);
+    int rc = LB_OK;
+    if ((rc = check_hip(hipMalloc(&h->buf[0], pb), "hipMalloc populations")) ||
+        (rc = check_hip(hipMalloc(&h->buf[1], pb), "hipMalloc populations")) ||
+        (rc = check_hip(hipMalloc(&h->phi, N * (h->p.storage == LB_STORE_F64 ? 8 : 4)), "hipMalloc phase field")) ||
+        (rc = check_hip(hipMalloc((void**)&h->partial, sizeof(Neu) * NTOT * kTotalsBlocks), "hipMalloc partials")) ||
+        (rc = check_hip(hipMalloc((void**)&h->dtot, sizeof(double) * 2 * NTOT), "hipMalloc totals"))) {
+        release(h);
+        return rc;
+    }
+    *out = h;
+    return LB_OK;
+}
+
+int lb_destroy(lb_t* h) {
+    if (!h) return fail(LB_EINVAL, "handle is NULL");
+    (void)hipStreamSynchronize(h->stream);
+    release(h);
+    return LB_OK;
+}
+
+int lb_init_fields(lb_t* h, const void* rho_r, const void* rho_b, const void* u, int32_t dtype,
+                   int32_t on_device) {
+    if (!h) return fail(LB_EINVAL, "handle is NULL");
+    if (!rho_r || !rho_b) return fail(LB_EINVAL, "rho_r and rho_b are required");
+    if (dtype != LB_DTYPE_F64 && dtype != LB_DTYPE_F32) return fail(LB_EINVAL, "dtype must be LB_DTYPE_F64 or LB_DTYPE_F32");
+    const size_t N = (size_t)h->g.N;
+    const size_t es = dtype == LB_DTYPE_F64 ? 8 : 4;
+    if (!on_device) {
+        // host inputs: reject non-physical densities before touching the state
+        for (size_t s = 0; s < N; ++s) {
+            const double a = dtype == LB_DTYPE_F64 ? ((const double*)rho_r)[s] : ((const float*)rho_r)[s];
+            const double b = dtype == LB_DTYPE_F64 ? ((const double*)rho_b)[s] : ((const float*)rho_b)[s];
+            if (!(a >= 0.0) || !(b >= 0.0) || !(a + b > 0.0) || !std::isfinite(a + b))
+                return fail(LB_EINVAL, "densities must be finite, >= 0, with rho_r + rho_b > 0");
+        }
+    }
+    // 16-bit lattices keep the initial state raw (FP32) until their first step.
+    const bool split = h->p.storage >= LB_STORE_F16;
+    if (split && !h->pending) {
+        int rc = check_hip(hipMalloc(&h->pending, pop_bytes(LB_STORE_F32, N)), "hipMalloc initial state");
+        if (rc) return rc;
+    }
+    void *d_rr = nullptr, *d_rb = nullptr, *d_u = nullptr, *scratch = nullptr;
+    if (!on_device) {
+        int rc = check_hip(hipMalloc(&scratch, 5 * N * es), "hipMalloc staging");
+        if (rc) return rc;
+    }
+    int rc = copy_in(rho_r, on_device, N * es, &d_rr, scratch, h->stream);
+    if (!rc) rc = copy_in(rho_b, on_device, N * es, &d_rb, scratch ? (char*)scratch + N * es : nullptr, h->stream);
+    if (!rc && u) rc = copy_in(u, on_device, 3 * N * es, &d_u, scratch ? (char*)scratch + 2 * N * es : nullptr, h->stream);
+    if (!rc) {
+        LatticeView v = view_of(h);
+        rc = launch_init(v, d_rr, d_rb, d_u, dtype);
+    }
+    if (scratch) {
+        (void)hipStreamSynchronize(h->stream);
+        (void)hipFree(scratch);
+    }
+    if (rc) return rc;
+    h->initialised = true;
+    h->steps = 0;
+    return LB_OK;
+}
+
+int lb_step(lb_t* h, int32_t n) {
+    if (!h) return fail(LB_EINVAL, "handle is NULL");
+    if (n < 0) return fail(LB_EINVAL, "n must be >= 0");
+    if (!h->initialised) return fail(LB_ESTATE, "lb_step before lb_init_fields");
+    for (int32_t k = 0; k < n; ++k) {
+        LatticeView v = view_of(h);
+        int rc = launch_step(v, h->kernel);
+        if (rc) return rc;
+        if (h->pending) {
+            // the first step consumed the raw initial state
+            (void)hipStreamSynchronize(h->stream);
+            (void)hipFree(h->pending);
+            h->pending = nullptr;
+        }
+        h->cur ^= 1;
+        h->steps++;
+    }
+    return LB_OK;
+}
+
+int lb_step_timed(lb_t* h, int32_t n, double kernel_ms[3]) {
+    if (!h || !kernel_ms) return fail(LB_EINVAL, "NULL argument");
+    if (n < 1) return fail(LB_EINVAL, "n must be >= 1");
+    if (!h->initialised) return fail(LB_ESTATE, "lb_step_timed before lb_init_fields");
+    StepEvents* ev = new (std::nothrow) StepEvents[n]();
+    if (!ev) return fail(LB_ENOMEM, "host allocation failed");
+    int rc = LB_OK;
+    int made = 0;
+    for (; made < n && !rc; ++made)
+        for (int k = 0; k < 3 && !rc; ++k) rc = check_hip(hipEventCreate(&ev[made].ev[k]), "hipEventCreate");
+    for (int32_t k = 0; k < n && !rc; ++k) {
+        LatticeView v = view_of(h);
+        rc = launch_step(v, h->kernel, &ev[k]);
+        if (rc) break;
+        if (h->pending) {
+            (void)hipStreamSynchronize(h->stream);
+            (void)hipFree(h->pending);
+            h->pending = nullptr;
+        }
+        h->cur ^= 1;
+        h->steps++;
+    }
+    if (!rc) rc = check_hip(hipStreamSynchronize(h->stream), "sync");
+    double a = 0, b = 0, c = 0;
+    if (!rc) {
+        for (int32_t k = 0; k < n; ++k) {
+            float t01 = 0, t12 = 0, t02 = 0;
+            if (h->kernel == LB_KERNEL_TWOPASS) (void)hipEventElapsedTime(&t01, ev[k].ev[0], ev[k].ev[1]);
+            (void)hipEventElapsedTime(&t12, h->kernel == LB_KERNEL_TWOPASS ? ev[k].ev[1] : ev[k].ev[0], ev[k].ev[2]);
+            (void)hipEventElapsedTime(&t02, ev[k].ev[0], ev[k].ev[2]);
+            a += t01;
+            b += t12;
+            c += t02;
+        }
+        kernel_ms[0] = a / n;
+        kernel_ms[1] = b / n;
+        kernel_ms[2] = c / n;
+    }
+    for (int k = 0; k < n; ++k)
+        for (int e = 0; e < 3; ++e)
+            if (ev[k].ev[e]) (void)hipEventDestroy(ev[k].ev[e]);
+    delete[] ev;
+    return rc;
+}
+
+int lb_moments(lb_t* h, void* rho_r, void* rho_b, void* mom, int32_t dtype, int32_t on_device,
+               double totals[14]) {
+    if (!h) return fail(LB_EINVAL, "handle is NULL");
+    if (!h->initialised) return fail(LB_ESTATE, "lb_moments before lb_init_fields");
+    if (dtype != LB_DTYPE_F64 && dtype != LB_DTYPE_F32) return fail(LB_EINVAL, "bad dtype");
+    const size_t N = (size_t)h->g.N;
+    const size_t es = dtype == LB_DTYPE_F64 ? 8 : 4;
+    LatticeView v = view_of(h);
+    int rc = LB_OK;
+    if (rho_r || rho_b || mom) {
+        void* scratch = nullptr;
+        if (!on_device) {
+            rc = check_hip(hipMalloc(&scratch, 5 * N * es), "hipMalloc staging");
+            if (rc) return rc;
+        }
+        char* base = (char*)scratch;
+        void* o_rr = rho_r ? (on_device ? rho_r : base) : nullptr;
+        void* o_rb = rho_b ? (on_device ? rho_b : base + N * es) : nullptr;
+        void* o_j = mom ? (on_device ? mom : base + 2 * N * es) : nullptr;
+        rc = launch_moments(v, o_rr, o_rb, o_j, dtype);
+        if (!rc && !on_device) {
+            if (rho_r) rc = check_hip(hipMemcpyAsync(rho_r, o_rr, N * es, hipMemcpyDeviceToHost, h->stream), "D2H");
+            if (!rc && rho_b) rc = check_hip(hipMemcpyAsync(rho_b, o_rb, N * es, hipMemcpyDeviceToHost, h->stream), "D2H");
+            if (!rc && mom) rc = check_hip(hipMemcpyAsync(mom, o_j, 3 * N * es, hipMemcpyDeviceToHost, h->stream), "D2H");
+            if (!rc) rc = check_hip(hipStreamSynchronize(h->stream), "sync");
+        }
+        if (scratch) {
+            (void)hipStreamSynchronize(h->stream);
+            (void)hipFree(scratch);
+        }
+        if (rc) return rc;
+    }
+    if (totals) {
+        rc = launch_totals(v, h->partial, h->dtot);
+        if (!rc) rc = check_hip(hipMemcpyAsync(totals, h->dtot, sizeof(double) * 2 * NTOT, hipMemcpyDeviceToHost, h->stream), "D2H totals");
+        if (!rc) rc = check_hip(hipStreamSynchronize(h->stream), "sync");
+    }
+    return rc;
+}
+
+int lb_get_state(lb_t* h, void* f, int32_t dtype, int32_t on_device) {
+    if (!h || !f) return fail(LB_EINVAL, "NULL argument");
+    if (!h->initialised) return fail(LB_ESTATE, "lb_get_state before lb_init_fields");
+    if (dtype != LB_DTYPE_F64 && dtype != LB_DTYPE_F32) return fail(LB_EINVAL, "bad dtype");
+    const size_t bytes = 2 * Q * (size_t)h->g.N * (dtype == LB_DTYPE_F64 ? 8 : 4);
+    void* out = f;
+    if (!on_device) {
+        int rc = check_hip(hipMalloc(&out, bytes), "hipMalloc staging");
+        if (rc) return rc;
+    }
+    LatticeView v = view_of(h);
+    int rc = launch_export(v, out, dtype);
+    if (!rc && !on_device) {
+        rc = check_hip(hipMemcpyAsync(f, out, bytes, hipMemcpyDeviceToHost, h->stream), "D2H state");
+        if (!rc) rc = check_hip(hipStreamSynchronize(h->stream), "sync");
+    }
+    if (!on_device) {
+        (void)hipStreamSynchronize(h->stream);
+        (void)hipFree(out);
+    }
+    return rc;
+}
+
+int lb_set_state(lb_t* h, const void* f, int32_t dtype, int32_t on_device) {
+    if (!h || !f) return fail(LB_EINVAL, "NULL argument");
+    if (dtype != LB_DTYPE_F64 && dtype != LB_DTYPE_F32) return fail(LB_EINVAL, "bad dtype");
+    const size_t N = (size_t)h->g.N;
+    const size_t bytes = 2 * Q * N * (dtype == LB_DTYPE_F64 ? 8 : 4);
+    const bool split = h->p.storage >= LB_STORE_F16;
+    if (split && !h->pending) {
+        int rc = check_hip(hipMalloc(&h->pending, pop_bytes(LB_STORE_F32, N)), "hipMalloc raw state");
+        if (rc) return rc;
+    }
+    const void* in = f;
+    void* staging = nullptr;
+    if (!on_device) {
+        int rc = check_hip(hipMalloc(&staging, bytes), "hipMalloc staging");
+        if (!rc) rc = check_hip(hipMemcpyAsync(staging, f, bytes, hipMemcpyHostToDevice, h->stream), "H2D state");
+        if (rc) {
+            if (staging) (void)hipFree(staging);
+            return rc;
+        }
+        in = staging;
+    }
+    LatticeView v = view_of(h);
+    int rc = launch_import(v, in, dtype);
+    if (staging) {
+        (void)hipStreamSynchronize(h->stream);
+        (void)hipFree(staging);
+    }
+    if (rc) return rc;
+    h->initialised = true;
+    return LB_OK;
+}
+
+int64_t lb_state_bytes(const lb_t* h) {
+    if (!h) return -1;
+    return (int64_t)pop_bytes(h->p.storage, (size_t)h->g.N);
+}
+
+int lb_save_raw(lb_t* h, void* dst, int32_t on_device) {
+    if (!h || !dst) return fail(LB_EINVAL, "NULL argument");
+    if (!h->initialised) return fail(LB_ESTATE, "no state yet");
+    if (h->pending) return fail(LB_ESTATE, "16-bit lattice holds a raw initial state until its first step; use lb_get_state");
+    const size_t b = pop_bytes(h->p.storage, (size_t)h->g.N);
+    int rc = check_hip(hipMemcpyAsync(dst, h->buf[h->cur], b, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, h->stream), "copy raw state");
+    if (!rc && !on_device) rc = check_hip(hipStreamSynchronize(h->stream), "sync");
+    return rc;
+}
+
+int lb_load_raw(lb_t* h, const void* src, int32_t on_device) {
+    if (!h || !src) return fail(LB_EINVAL, "NULL argument");
+    const size_t b = pop_bytes(h->p.storage, (size_t)h->g.N);
+    int rc = check_hip(hipMemcpyAsync(h->buf[h->cur], src, b, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, h->stream), "copy raw state");
+    if (!rc && !on_device) rc = check_hip(hipStreamSynchronize(h->stream), "sync");
+    if (rc) return rc;
+    if (h->pending) {
+        (void)hipStreamSynchronize(h->stream);
+        (void)hipFree(h->pending);
+        h->pending = nullptr;
+    }
+    h->initialised = true;
+    return LB_OK;
+}
+
+int64_t lb_step_count(const lb_t* h) { return h ? h->steps : -1; }
+
+int lb_kernel_in_use(const lb_t* h) { return h ? h->kernel : LB_EINVAL; }
+
+}  // extern "C"

@@ -1,0 +1,50 @@
+// lb_internal.hpp -- declarations shared by the host translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "lb.h"
+#include "lb_kernels.hpp"
+
+namespace lbm {
+
+// Blocks of the compensated-reduction kernel (fixed, so totals are bitwise
+// reproducible for a given lattice).
+constexpr int kTotalsBlocks = 512;
+
+// What a launch needs to know about one lattice.
+struct LatticeView {
+    const lb_params* p;
+    Geom g;
+    hipStream_t stream;
+    void* cur;      // post-collision buffer holding the current state
+    void* nxt;      // buffer the next step writes
+    void* pending;  // raw FP32 current state of a 16-bit lattice (else null)
+    void* phi;      // phase-field scratch
+    Coeffs<double> cd;
+    Coeffs<float> cf;
+};
+
+int set_error(int code, const char* msg);
+int validate_params(const lb_params* p, std::string& why);
+template <typename R>
+Coeffs<R> make_coeffs(const lb_params& p);
+Geom make_geom(const lb_params& p);
+size_t pop_bytes(int storage, size_t N);
+
+int choose_kernel(const lb_params& p);
+// Events recorded around the passes of one step (null = no timing):
+// ev[0] before the step, ev[1] between the phase and the collide pass (equal
+// to ev[0] for the fused kernel), ev[2] after the step.
+struct StepEvents {
+    hipEvent_t ev[3];
+};
+int launch_step(const LatticeView& v, int kernel, const StepEvents* t = nullptr);
+int launch_init(const LatticeView& v, const void* rr, const void* rb, const void* u, int dtype);
+int launch_import(const LatticeView& v, const void* f, int dtype);
+int launch_export(const LatticeView& v, void* out, int dtype);
+int launch_moments(const LatticeView& v, void* rr, void* rb, void* j, int dtype);
+int launch_totals(const LatticeView& v, Neu* partial, double* dtot);
+
+}  // namespace lbm

@@ -1,0 +1,495 @@
+// lb_kernels.hpp -- population storage policies and the two-pass kernels
+// (phase-field pass, then collide-and-stream pass), plus init, export,
+// moments and compensated reductions.  Included by the translation units
+// that instantiate and launch them.
+#pragma once
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "d3q19.hpp"
+
+namespace lbm {
+
+// Lattice geometry.  Site index s = x + nx*(y + ny*z) (< 2^31).
+struct Geom {
+    int nx, ny, nz;
+    int wx, wy, wz;  // 1 = halfway bounce-back walls on that axis
+    int nxy;
+    int N;
+};
+
+__device__ __forceinline__ void site_xyz(const Geom& g, int s, int& x, int& y, int& z) {
+    z = s / g.nxy;
+    const int r = s - z * g.nxy;
+    y = r / g.nx;
+    x = r - y * g.nx;
+}
+
+__device__ __forceinline__ int site_of(const Geom& g, int x, int y, int z) {
+    return x + g.nx * (y + g.ny * z);
+}
+
+// Coordinate of the site a population arriving at v - c came from, for a
+// unit step c: wraps on a periodic axis, flags a wall crossing.
+__device__ __forceinline__ int step_back(int v, int c, int n, int wall, bool& bb) {
+    int t = v - c;
+    if (t < 0) {
+        if (wall) bb = true;
+        t += n;
+    } else if (t >= n) {
+        if (wall) bb = true;
+        t -= n;
+    }
+    return t;
+}
+
+// Neighbour coordinate for the gradient stencil: wrap on periodic axes; on a
+// wall axis the mirror image across the halfway wall.
+__device__ __forceinline__ int stencil_coord(int v, int n, int wall) {
+    if (v < 0) return wall ? -1 - v : v + n;
+    if (v >= n) return wall ? 2 * n - 1 - v : v - n;
+    return v;
+}
+
+// Pull source of direction i at (x,y,z): the upstream site, or the site
+// itself in the opposite direction when the upstream site lies beyond a wall.
+__device__ __forceinline__ int pull_source(const Geom& g, int i, int x, int y, int z, int s, int& d) {
+    using L = Lattice;
+    bool bb = false;
+    const int xs = L::cx[i] ? step_back(x, L::cx[i], g.nx, g.wx, bb) : x;
+    const int ys = L::cy[i] ? step_back(y, L::cy[i], g.ny, g.wy, bb) : y;
+    const int zs = L::cz[i] ? step_back(z, L::cz[i], g.nz, g.wz, bb) : z;
+    d = bb ? L::opp[i] : i;
+    return bb ? s : site_of(g, xs, ys, zs);
+}
+
+// ---------------------------------------------------------------------------
+// Storage policies.  pull() gathers the post-streaming populations of a site
+// from the post-collision buffer of the previous step; store() writes the
+// site's post-collision populations in place (aligned, coalesced).
+// ---------------------------------------------------------------------------
+
+// Raw populations [2][19][N] of type T.
+template <typename T>
+struct RawPop {
+    T* f;
+    size_t N;
+
+    template <typename R>
+    __device__ __forceinline__ void pull(const Geom& g, int s, int x, int y, int z, R (&fr)[Q],
+                                         R (&fb)[Q]) const {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            int d;
+            const int src = pull_source(g, i, x, y, z, s, d);
+            fr[i] = R(f[(size_t)d * N + src]);
+            fb[i] = R(f[(size_t)(Q + d) * N + src]);
+        }
+    }
+    template <typename R>
+    __device__ __forceinline__ void store(int s, const R (&fr)[Q], const R (&fb)[Q],
+                                          const SiteTotals<R>&) const {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            __builtin_nontemporal_store(T(fr[i]), &f[(size_t)i * N + s]);
+            __builtin_nontemporal_store(T(fb[i]), &f[(size_t)(Q + i) * N + s]);
+        }
+    }
+    static constexpr bool needs_totals = false;
+};
+
+template <typename H>
+struct Half;
+template <>
+struct Half<__half> {
+    static __device__ __forceinline__ float to_f(__half h) { return __half2float(h); }
+    static __device__ __forceinline__ __half from_f(float v) { return __float2half_rn(v); }
+};
+template <>
+struct Half<__hip_bfloat16> {
+    static __device__ __forceinline__ float to_f(__hip_bfloat16 h) { return __bfloat162float(h); }
+    static __device__ __forceinline__ __hip_bfloat16 from_f(float v) { return __float2bfloat16(v); }
+};
+
+// 16-bit moment-split storage.  Per site, 8 FP32 values rec[8][N]: density,
+// velocity (3), red fraction, recolouring vector (3) of the post-collision
+// state; per direction dev[19][N]: the total post-collision population minus
+// its equilibrium rho f^eq_unit(u), times `scale`, in 16 bits.  The red part
+// of direction i is x_r f*_i + w_i (c_i . v)/|c_i|, which is exactly the form
+// recolouring produces, so colour is carried in FP32.
+template <typename H>
+struct SplitPop {
+    float* rec;
+    H* dev;
+    size_t N;
+    float scale, inv_scale;
+
+    template <typename R>
+    __device__ __forceinline__ void pull(const Geom& g, int s, int x, int y, int z, R (&fr)[Q],
+                                         R (&fb)[Q]) const {
+        using L = Lattice;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            int d;
+            const int src = pull_source(g, i, x, y, z, s, d);
+            const float rho = rec[src], ux = rec[N + src], uy = rec[2 * N + src],
+                        uz = rec[3 * N + src], xr = rec[4 * N + src], vx = rec[5 * N + src],
+                        vy = rec[6 * N + src], vz = rec[7 * N + src];
+            const float dv = Half<H>::to_f(dev[(size_t)d * N + src]) * inv_scale;
+            // direction d is i, or its opposite after a bounce-back (same shell)
+            const float sg = (d == i) ? 1.0f : -1.0f;
+            const float cdx = sg * float(L::cx[i]), cdy = sg * float(L::cy[i]), cdz = sg * float(L::cz[i]);
+            const float cu = cdx * ux + cdy * uy + cdz * uz;
+            const float uu = ux * ux + uy * uy + uz * uz;
+            const float w = weight<float>(i);
+            const float ic = inv_clen<float>(i);
+            const float fs = rho * (w * (1.0f + 3.0f * cu + 4.5f * cu * cu - 1.5f * uu)) + dv;
+            const float r = xr * fs + w * (cdx * vx + cdy * vy + cdz * vz) * ic;
+            fr[i] = R(r);
+            fb[i] = R(fs - r);
+        }
+    }
+    template <typename R>
+    __device__ __forceinline__ void store(int s, const R (&fr)[Q], const R (&fb)[Q],
+                                          const SiteTotals<R>& t) const {
+        const float rho = float(t.rho), ux = float(t.ux), uy = float(t.uy), uz = float(t.uz);
+        __builtin_nontemporal_store(rho, &rec[s]);
+        __builtin_nontemporal_store(ux, &rec[N + s]);
+        __builtin_nontemporal_store(uy, &rec[2 * N + s]);
+        __builtin_nontemporal_store(uz, &rec[3 * N + s]);
+        __builtin_nontemporal_store(float(t.xr), &rec[4 * N + s]);
+        __builtin_nontemporal_store(float(t.vx), &rec[5 * N + s]);
+        __builtin_nontemporal_store(float(t.vy), &rec[6 * N + s]);
+        __builtin_nontemporal_store(float(t.vz), &rec[7 * N + s]);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const float fs = float(fr[i]) + float(fb[i]);
+            const float e = rho * feq_unit<float>(i, ux, uy, uz);
+            dev[(size_t)i * N + s] = Half<H>::from_f((fs - e) * scale);
+        }
+    }
+    static constexpr bool needs_totals = true;
+};
+
+// ---------------------------------------------------------------------------
+// Phase field and colour gradient.
+// ---------------------------------------------------------------------------
+
+// G(x) = 3 sum_i w_i phi(x + c_i) c_i, mirror sites beyond walls.
+template <typename R>
+__device__ __forceinline__ void gradient(const Geom& g, const R* __restrict__ phi, int x, int y,
+                                         int z, R& gx, R& gy, R& gz) {
+    using L = Lattice;
+    R ax = R(0), ay = R(0), az = R(0);
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const int xn = L::cx[i] ? stencil_coord(x + L::cx[i], g.nx, g.wx) : x;
+        const int yn = L::cy[i] ? stencil_coord(y + L::cy[i], g.ny, g.wy) : y;
+        const int zn = L::cz[i] ? stencil_coord(z + L::cz[i], g.nz, g.wz) : z;
+        const R p = weight<R>(i) * phi[site_of(g, xn, yn, zn)];
+        if (L::cx[i]) ax += L::cx[i] > 0 ? p : -p;
+        if (L::cy[i]) ay += L::cy[i] > 0 ? p : -p;
+        if (L::cz[i]) az += L::cz[i] > 0 ? p : -p;
+    }
+    gx = R(3) * ax;
+    gy = R(3) * ay;
+    gz = R(3) * az;
+}
+
+__device__ __forceinline__ int wrap_any(int v, int n) {
+    int r = v % n;
+    return r < 0 ? r + n : r;
+}
+
+// Near-contact force A_h(h) G at (x,y,z): interface sites probe their outward
+// normal ray x + round(k n), k = 1..K, for an interface site whose gradient
+// opposes G; a sample beyond a wall ends the probe.
+template <typename R>
+__device__ __forceinline__ void near_contact(const Geom& g, const R* __restrict__ phi, int x, int y,
+                                             int z, R gx, R gy, R gz, const Coeffs<R>& c, R& Fx,
+                                             R& Fy, R& Fz) {
+    const R gm = sqrt(gx * gx + gy * gy + gz * gz);
+    if (!(gm >= c.g_iface)) return;
+    const R nx = -gx / gm, ny = -gy / gm, nz = -gz / gm;
+    int h = 0;
+    for (int k = 1; k <= c.nc_range; ++k) {
+        int px = x + (int)round(R(k) * nx);
+        int py = y + (int)round(R(k) * ny);
+        int pz = z + (int)round(R(k) * nz);
+        if (g.wx) { if (px < 0 || px >= g.nx) break; } else px = wrap_any(px, g.nx);
+        if (g.wy) { if (py < 0 || py >= g.ny) break; } else py = wrap_any(py, g.ny);
+        if (g.wz) { if (pz < 0 || pz >= g.nz) break; } else pz = wrap_any(pz, g.nz);
+        R qx, qy, qz;
+        gradient<R>(g, phi, px, py, pz, qx, qy, qz);
+        const R qm = sqrt(qx * qx + qy * qy + qz * qz);
+        const R dot = qx * gx + qy * gy + qz * gz;
+        if (qm >= c.g_iface && dot < R(0)) {
+            h = k;
+            break;
+        }
+    }
+    const R ah = nc_amplitude<R>(h, c);
+    Fx += ah * gx;
+    Fy += ah * gy;
+    Fz += ah * gz;
+}
+
+// ---------------------------------------------------------------------------
+// Two-pass step.
+// ---------------------------------------------------------------------------
+
+// Pass 1: phi = (rho_r - rho_b)/rho of the post-streaming state.
+template <typename R, typename Src>
+__global__ __launch_bounds__(256) void phase_kernel(Geom g, Src src, R* __restrict__ phi) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= g.N) return;
+    int x, y, z;
+    site_xyz(g, s, x, y, z);
+    R fr[Q], fb[Q];
+    src.pull(g, s, x, y, z, fr, fb);
+    R rr = R(0), rb = R(0);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        rr += fr[i];
+        rb += fb[i];
+    }
+    phi[s] = (rr - rb) / (rr + rb);
+}
+
+// Pass 2: pull, colour gradient, near-contact, collision, store.
+template <typename R, typename Src, typename Dst>
+__global__ __launch_bounds__(256) void collide_kernel(Geom g, Src src, Dst dst,
+                                                      const R* __restrict__ phi, Coeffs<R> c) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= g.N) return;
+    int x, y, z;
+    site_xyz(g, s, x, y, z);
+    R fr[Q], fb[Q];
+    src.pull(g, s, x, y, z, fr, fb);
+    R gx, gy, gz;
+    gradient<R>(g, phi, x, y, z, gx, gy, gz);
+    R Fx = c.fx, Fy = c.fy, Fz = c.fz;
+    if (c.nc_range > 0 && c.nc_strength != R(0)) near_contact<R>(g, phi, x, y, z, gx, gy, gz, c, Fx, Fy, Fz);
+    SiteTotals<R> tot;
+    collide<R>(fr, fb, gx, gy, gz, Fx, Fy, Fz, c, &tot);
+    dst.store(s, fr, fb, tot);
+}
+
+// ---------------------------------------------------------------------------
+// Init / import (into raw storage), export, moments.
+// ---------------------------------------------------------------------------
+
+// Post-collision buffer whose pull gives f^eq(rho_k, u) at every site:
+// buf_j(y) = f^eq_j(y + c_j), or f^eq_opp(j)(y) when y + c_j lies beyond a wall.
+template <typename T, typename In>
+__global__ __launch_bounds__(256) void init_raw_kernel(Geom g, T* __restrict__ f, const In* rr,
+                                                       const In* rb, const In* u) {
+    using L = Lattice;
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= g.N) return;
+    int x, y, z;
+    site_xyz(g, s, x, y, z);
+    const size_t N = (size_t)g.N;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+        // the target of direction j from s is where the population streams to
+        bool bb = false;
+        const int xt = L::cx[j] ? step_back(x, -L::cx[j], g.nx, g.wx, bb) : x;
+        const int yt = L::cy[j] ? step_back(y, -L::cy[j], g.ny, g.wy, bb) : y;
+        const int zt = L::cz[j] ? step_back(z, -L::cz[j], g.nz, g.wz, bb) : z;
+        const int t = bb ? s : site_of(g, xt, yt, zt);
+        const int d = bb ? L::opp[j] : j;
+        double ux = 0, uy = 0, uz = 0;
+        if (u) {
+            ux = double(u[t]);
+            uy = double(u[N + t]);
+            uz = double(u[2 * N + t]);
+        }
+        double e;
+        {
+            const double cu = L::cx[d] * ux + L::cy[d] * uy + L::cz[d] * uz;
+            const double uu = ux * ux + uy * uy + uz * uz;
+            e = weight<double>(d) * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+        }
+        f[(size_t)j * N + s] = T(double(rr[t]) * e);
+        f[(size_t)(Q + j) * N + s] = T(double(rb[t]) * e);
+    }
+}
+
+// Import of post-streaming populations fin[2][19][N] into raw post-collision
+// storage (the inverse of the pull).
+template <typename T, typename In>
+__global__ __launch_bounds__(256) void import_raw_kernel(Geom g, T* __restrict__ f,
+                                                         const In* __restrict__ fin) {
+    using L = Lattice;
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= g.N) return;
+    int x, y, z;
+    site_xyz(g, s, x, y, z);
+    const size_t N = (size_t)g.N;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+        bool bb = false;
+        const int xt = L::cx[j] ? step_back(x, -L::cx[j], g.nx, g.wx, bb) : x;
+        const int yt = L::cy[j] ? step_back(y, -L::cy[j], g.ny, g.wy, bb) : y;
+        const int zt = L::cz[j] ? step_back(z, -L::cz[j], g.nz, g.wz, bb) : z;
+        const int t = bb ? s : site_of(g, xt, yt, zt);
+        const int d = bb ? L::opp[j] : j;
+        f[(size_t)j * N + s] = T(fin[(size_t)d * N + t]);
+        f[(size_t)(Q + j) * N + s] = T(fin[(size_t)(Q + d) * N + t]);
+    }
+}
+
+// Export of the post-streaming populations.
+template <typename R, typename Src, typename Out>
+__global__ __launch_bounds__(256) void export_kernel(Geom g, Src src, Out* __restrict__ out) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= g.N) return;
+    int x, y, z;
+    site_xyz(g, s, x, y, z);
+    R fr[Q], fb[Q];
+    src.pull(g, s, x, y, z, fr, fb);
+    const size_t N = (size_t)g.N;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        out[(size_t)i * N + s] = Out(fr[i]);
+        out[(size_t)(Q + i) * N + s] = Out(fb[i]);
+    }
+}
+
+// Moments rho_r, rho_b, j of the post-streaming state (any output may be null).
+template <typename R, typename Src, typename Out>
+__global__ __launch_bounds__(256) void moments_kernel(Geom g, Src src, Out* rr_out, Out* rb_out,
+                                                      Out* j_out) {
+    using L = Lattice;
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= g.N) return;
+    int x, y, z;
+    site_xyz(g, s, x, y, z);
+    R fr[Q], fb[Q];
+    src.pull(g, s, x, y, z, fr, fb);
+    R rr = R(0), rb = R(0), jx = R(0), jy = R(0), jz = R(0);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        rr += fr[i];
+        rb += fb[i];
+        const R t = fr[i] + fb[i];
+        if (L::cx[i]) jx += L::cx[i] > 0 ? t : -t;
+        if (L::cy[i]) jy += L::cy[i] > 0 ? t : -t;
+        if (L::cz[i]) jz += L::cz[i] > 0 ? t : -t;
+    }
+    const size_t N = (size_t)g.N;
+    if (rr_out) rr_out[s] = Out(rr);
+    if (rb_out) rb_out[s] = Out(rb);
+    if (j_out) {
+        j_out[s] = Out(jx);
+        j_out[N + s] = Out(jy);
+        j_out[2 * N + s] = Out(jz);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic compensated FP64 totals.
+// ---------------------------------------------------------------------------
+constexpr int NTOT = 7;  // red mass, blue mass, jx, jy, jz, kinetic energy, bad sites
+
+struct Neu {
+    double s, c;
+};
+__device__ __forceinline__ void neu_add(Neu& a, double x) {
+    const double t = a.s + x;
+    if (fabs(a.s) >= fabs(x))
+        a.c += (a.s - t) + x;
+    else
+        a.c += (x - t) + a.s;
+    a.s = t;
+}
+__device__ __forceinline__ void neu_merge(Neu& a, const Neu& b) {
+    neu_add(a, b.s);
+    a.c += b.c;
+}
+
+// Block-level fixed-order reduction: wave shuffles, then the 4 wave results
+// through LDS in wave order.  Every thread must call it.
+__device__ __forceinline__ void block_reduce(Neu (&acc)[NTOT], Neu* lds /* [4][NTOT] */) {
+#pragma unroll
+    for (int q = 0; q < NTOT; ++q) {
+        for (int off = 32; off >= 1; off >>= 1) {
+            Neu o;
+            o.s = __shfl_down(acc[q].s, off, 64);
+            o.c = __shfl_down(acc[q].c, off, 64);
+            neu_merge(acc[q], o);
+        }
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0)
+        for (int q = 0; q < NTOT; ++q) lds[wave * NTOT + q] = acc[q];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 0; q < NTOT; ++q) {
+            Neu r = lds[q];
+            for (int w = 1; w < (int)(blockDim.x >> 6); ++w) neu_merge(r, lds[w * NTOT + q]);
+            acc[q] = r;
+        }
+    }
+}
+
+template <typename R, typename Src>
+__global__ __launch_bounds__(256) void totals_kernel(Geom g, Src src, Neu* __restrict__ partial) {
+    using L = Lattice;
+    __shared__ Neu lds[4 * NTOT];
+    Neu acc[NTOT];
+#pragma unroll
+    for (int q = 0; q < NTOT; ++q) acc[q] = Neu{0.0, 0.0};
+    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < g.N; s += gridDim.x * blockDim.x) {
+        int x, y, z;
+        site_xyz(g, s, x, y, z);
+        R fr[Q], fb[Q];
+        src.pull(g, s, x, y, z, fr, fb);
+        double rr = 0, rb = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            rr += double(fr[i]);
+            rb += double(fb[i]);
+            const double t = double(fr[i]) + double(fb[i]);
+            if (L::cx[i]) jx += L::cx[i] > 0 ? t : -t;
+            if (L::cy[i]) jy += L::cy[i] > 0 ? t : -t;
+            if (L::cz[i]) jz += L::cz[i] > 0 ? t : -t;
+        }
+        const double rho = rr + rb;
+        const bool bad = !(rho > 0.0) || !isfinite(rho) || !isfinite(jx) || !isfinite(jy) ||
+                         !isfinite(jz);
+        neu_add(acc[0], rr);
+        neu_add(acc[1], rb);
+        neu_add(acc[2], jx);
+        neu_add(acc[3], jy);
+        neu_add(acc[4], jz);
+        neu_add(acc[5], bad ? 0.0 : 0.5 * (jx * jx + jy * jy + jz * jz) / rho);
+        neu_add(acc[6], bad ? 1.0 : 0.0);
+    }
+    block_reduce(acc, lds);
+    if (threadIdx.x == 0)
+        for (int q = 0; q < NTOT; ++q) partial[blockIdx.x * NTOT + q] = acc[q];
+}
+
+// One block folds the per-block partials in block order.
+static __global__ __launch_bounds__(256) void totals_final_kernel(const Neu* __restrict__ partial, int nblocks,
+                                                           double* __restrict__ out) {
+    __shared__ Neu lds[4 * NTOT];
+    Neu acc[NTOT];
+#pragma unroll
+    for (int q = 0; q < NTOT; ++q) acc[q] = Neu{0.0, 0.0};
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
+        for (int q = 0; q < NTOT; ++q) neu_merge(acc[q], partial[b * NTOT + q]);
+    block_reduce(acc, lds);
+    if (threadIdx.x == 0)
+        for (int q = 0; q < NTOT; ++q) {
+            out[2 * q] = acc[q].s;
+            out[2 * q + 1] = acc[q].c;
+        }
+}
+
+}  // namespace lbm

@@ -1,0 +1,318 @@
+"""ctypes binding of liblb.so (include/lb.h), argument marshalling only.
+
+Every step of the update runs in the library's HIP kernels; this module only
+converts Python/numpy/torch arguments to the C ABI.  Importing it does not load
+the library; the first call does, and raises if the library is not built.
+Host arrays are numpy; device arrays are torch CUDA (HIP) tensors, passed by
+``data_ptr()``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+from .workloads import F64, F32, F16, BF16  # storage codes  # noqa: F401
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblb.so")
+
+LB_OK, LB_EINVAL, LB_ENOMEM, LB_EDEVICE, LB_ESTATE = 0, -1, -2, -3, -4
+KERNEL_AUTO, KERNEL_TWOPASS, KERNEL_FUSED = 0, 1, 2
+DTYPE_F64, DTYPE_F32 = 0, 1
+MAX_NC_RANGE = 4
+Q = 19
+
+
+class LbError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("liblb error %d: %s" % (code, msg))
+        self.code = code
+
+
+class lb_params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("bc", ctypes.c_int32 * 3),
+        ("storage", ctypes.c_int32), ("kernel", ctypes.c_int32),
+        ("tau_r", ctypes.c_double), ("tau_b", ctypes.c_double),
+        ("A", ctypes.c_double), ("beta", ctypes.c_double),
+        ("nc_strength", ctypes.c_double),
+        ("nc_range", ctypes.c_int32), ("scale_log2", ctypes.c_int32),
+        ("nc_hmin", ctypes.c_double),
+        ("body_force", ctypes.c_double * 3),
+        ("eps_g", ctypes.c_double), ("g_iface", ctypes.c_double),
+    ]
+
+
+def make_params(p: dict) -> lb_params:
+    """lb_params from a parameter dict (keys as in workloads.base_params)."""
+    s = lb_params()
+    s.nx, s.ny, s.nz = int(p["nx"]), int(p["ny"]), int(p["nz"])
+    for a in range(3):
+        s.bc[a] = int(p.get("bc", (0, 0, 0))[a])
+        s.body_force[a] = float(p.get("body_force", (0.0, 0.0, 0.0))[a])
+    s.storage = int(p.get("storage", F32))
+    s.kernel = int(p.get("kernel", KERNEL_AUTO))
+    s.tau_r, s.tau_b = float(p["tau_r"]), float(p["tau_b"])
+    s.A, s.beta = float(p.get("A", 0.0)), float(p.get("beta", 0.7))
+    s.nc_strength = float(p.get("nc_strength", 0.0))
+    s.nc_range = int(p.get("nc_range", 0))
+    s.scale_log2 = int(p.get("scale_log2", 0))
+    s.nc_hmin = float(p.get("nc_hmin", 2.0))
+    s.eps_g = float(p.get("eps_g", 0.0))
+    s.g_iface = float(p.get("g_iface", 0.0))
+    return s
+
+
+_lib = None
+
+
+def lib():
+    """Load liblb.so; raises if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("liblb.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+    # torch ships its own HIP runtime under the same soname; loading torch first
+    # makes liblb.so bind to that one, so the process holds a single runtime and
+    # torch streams and device pointers are valid in the library.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)
+    pp = ctypes.POINTER(lb_params)
+    sig = {
+        "lb_create": ([pp, vp, ctypes.POINTER(vp)], i32),
+        "lb_init_fields": ([vp, vp, vp, vp, i32, i32], i32),
+        "lb_step": ([vp, i32], i32),
+        "lb_moments": ([vp, vp, vp, vp, i32, i32, dp], i32),
+        "lb_step_timed": ([vp, i32, dp], i32),
+        "lb_get_state": ([vp, vp, i32, i32], i32),
+        "lb_set_state": ([vp, vp, i32, i32], i32),
+        "lb_state_bytes": ([vp], i64),
+        "lb_save_raw": ([vp, vp, i32], i32),
+        "lb_load_raw": ([vp, vp, i32], i32),
+        "lb_step_count": ([vp], i64),
+        "lb_kernel_in_use": ([vp], i32),
+        "lb_destroy": ([vp], i32),
+        "lb_last_error": ([], ctypes.c_char_p),
+        "lb_footprint_bytes": ([pp], i64),
+        "lb_batch_create": ([i32, i64, i32, i32, vp, ctypes.POINTER(vp)], i32),
+        "lb_batch_add": ([vp, pp, vp, vp, vp, i32, i32, ctypes.POINTER(i32)], i32),
+        "lb_batch_remove": ([vp, i32], i32),
+        "lb_batch_step": ([vp, i32], i32),
+        "lb_batch_moments": ([vp, i32, vp, vp, vp, i32, i32, dp], i32),
+        "lb_batch_get_state": ([vp, i32, vp, i32, i32], i32),
+        "lb_batch_job_steps": ([vp, i32], i64),
+        "lb_batch_free_bytes": ([vp], i64),
+        "lb_batch_destroy": ([vp], i32),
+    }
+    for name, (args, res) in sig.items():
+        if hasattr(L, name):
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+    _lib = L
+    return L
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise LbError(rc, lib().lb_last_error().decode())
+    return rc
+
+
+def _is_torch(a) -> bool:
+    return type(a).__module__.startswith("torch")
+
+
+def _arg(a, dtype_code: Optional[int] = None):
+    """(pointer, on_device, dtype_code, keepalive) of a numpy array or torch tensor."""
+    if a is None:
+        return None, 0, dtype_code, None
+    if _is_torch(a):
+        import torch
+        if not a.is_contiguous():
+            raise ValueError("device tensors must be contiguous")
+        code = {torch.float64: DTYPE_F64, torch.float32: DTYPE_F32}[a.dtype]
+        return ctypes.c_void_p(a.data_ptr()), int(a.is_cuda), code, a
+    arr = np.ascontiguousarray(a)
+    if arr.dtype not in (np.float64, np.float32):
+        arr = arr.astype(np.float64)
+    code = DTYPE_F64 if arr.dtype == np.float64 else DTYPE_F32
+    return ctypes.c_void_p(arr.ctypes.data), 0, code, arr
+
+
+def _stream_ptr(stream) -> ctypes.c_void_p:
+    if stream is None:
+        return ctypes.c_void_p(None)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+# ----------------------------------------------------------------------------
+# C-ABI names
+# ----------------------------------------------------------------------------
+
+def lb_create(params: dict, stream=None) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    prm = make_params(params)
+    _check(lib().lb_create(ctypes.byref(prm), _stream_ptr(stream), ctypes.byref(h)))
+    return h
+
+
+def lb_init_fields(h, rho_r, rho_b, u=None) -> None:
+    pr, dev, code, k1 = _arg(rho_r)
+    pb, dev2, code2, k2 = _arg(rho_b, code)
+    pu, dev3, code3, k3 = _arg(u, code)
+    if code2 != code or (u is not None and code3 != code) or dev2 != dev or (u is not None and dev3 != dev):
+        raise ValueError("rho_r, rho_b and u must share dtype and device")
+    _check(lib().lb_init_fields(h, pr, pb, pu, code, dev))
+
+
+def lb_step(h, n: int = 1) -> None:
+    _check(lib().lb_step(h, int(n)))
+
+
+def lb_step_timed(h, n: int):
+    """Run n steps timing each pass with HIP events; returns mean ms per step
+    of (phase pass, collide/fused pass, whole step)."""
+    out = (ctypes.c_double * 3)()
+    _check(lib().lb_step_timed(h, int(n), ctypes.cast(out, ctypes.POINTER(ctypes.c_double))))
+    return tuple(out[:])
+
+
+def lb_moments(h, rho_r=None, rho_b=None, mom=None, want_totals: bool = False):
+    """Fill the given output arrays (numpy host or torch device, same dtype);
+    return the 7 compensated totals (sum + correction) if requested."""
+    outs = [o for o in (rho_r, rho_b, mom) if o is not None]
+    code, dev = DTYPE_F64, 0
+    ptrs = []
+    for o in (rho_r, rho_b, mom):
+        if o is None:
+            ptrs.append(None)
+            continue
+        if _is_torch(o):
+            p, dev, code, _ = _arg(o)
+        else:
+            if not (isinstance(o, np.ndarray) and o.flags.c_contiguous):
+                raise ValueError("host outputs must be C-contiguous numpy arrays")
+            code = DTYPE_F64 if o.dtype == np.float64 else DTYPE_F32
+            p = ctypes.c_void_p(o.ctypes.data)
+        ptrs.append(p)
+    tot = (ctypes.c_double * 14)() if want_totals else None
+    _check(lib().lb_moments(h, ptrs[0], ptrs[1], ptrs[2], code, dev,
+                            ctypes.cast(tot, ctypes.POINTER(ctypes.c_double)) if tot else None))
+    if want_totals:
+        t = np.array(tot[:], dtype=np.float64).reshape(7, 2)
+        return t
+    return None
+
+
+def lb_get_state(h, out) -> None:
+    p, dev, code, _ = _arg(out) if _is_torch(out) else (ctypes.c_void_p(out.ctypes.data), 0,
+                                                         DTYPE_F64 if out.dtype == np.float64 else DTYPE_F32, out)
+    _check(lib().lb_get_state(h, p, code, dev))
+
+
+def lb_set_state(h, f) -> None:
+    p, dev, code, keep = _arg(f)
+    _check(lib().lb_set_state(h, p, code, dev))
+
+
+def lb_destroy(h) -> None:
+    _check(lib().lb_destroy(h))
+
+
+def lb_last_error() -> str:
+    return lib().lb_last_error().decode()
+
+
+def lb_footprint_bytes(params: dict) -> int:
+    prm = make_params(params)
+    return int(lib().lb_footprint_bytes(ctypes.byref(prm)))
+
+
+# ----------------------------------------------------------------------------
+# Convenience wrapper
+# ----------------------------------------------------------------------------
+
+class Lattice:
+    """One lattice owned by the library.  Host-side results are numpy arrays
+    shaped (nz, ny, nx) / (3, nz, ny, nx) / (2, 19, nz, ny, nx)."""
+
+    def __init__(self, params: dict, stream=None):
+        self.params = dict(params)
+        self.shape = (int(params["nz"]), int(params["ny"]), int(params["nx"]))
+        self.N = int(np.prod(self.shape))
+        self.h = lb_create(self.params, stream)
+
+    def init(self, rho_r, rho_b, u=None):
+        lb_init_fields(self.h, rho_r, rho_b, u)
+        return self
+
+    def step(self, n: int = 1):
+        lb_step(self.h, n)
+        return self
+
+    def moments(self):
+        rr = np.empty(self.shape)
+        rb = np.empty(self.shape)
+        j = np.empty((3,) + self.shape)
+        lb_moments(self.h, rr, rb, j)
+        return rr, rb, j
+
+    def totals(self):
+        return lb_moments(self.h, want_totals=True)
+
+    def state(self, dtype=np.float64):
+        out = np.empty((2, Q) + self.shape, dtype=dtype)
+        lb_get_state(self.h, out)
+        return out
+
+    def set_state(self, f):
+        lb_set_state(self.h, f)
+
+    @property
+    def steps(self) -> int:
+        return int(lib().lb_step_count(self.h))
+
+    @property
+    def kernel(self) -> int:
+        return int(lib().lb_kernel_in_use(self.h))
+
+    def state_bytes(self) -> int:
+        return int(lib().lb_state_bytes(self.h))
+
+    def save_raw(self) -> np.ndarray:
+        buf = np.empty(self.state_bytes(), dtype=np.uint8)
+        _check(lib().lb_save_raw(self.h, ctypes.c_void_p(buf.ctypes.data), 0))
+        return buf
+
+    def load_raw(self, buf: np.ndarray):
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        _check(lib().lb_load_raw(self.h, ctypes.c_void_p(buf.ctypes.data), 0))
+
+    def close(self):
+        if self.h is not None:
+            lb_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,212 @@
+"""GPU parity: the HIP path against the FP64 oracle, element by element.
+
+Tolerances (relative L2 over each of the 38 population fields and the two
+component densities, momentum against c_s ||rho||):
+  - FP64 storage: 1e-12 after 200 steps;
+  - FP32 storage: 1e-5 after 200 steps;
+  - 16-bit moment-split storage: the per-step representation error of the
+    non-equilibrium part (fp16: 2^-11 relative of a part ~1e-3 of the
+    population, bf16: 2^-8) bounds the state error; the gates are 2e-4 (fp16)
+    and 2e-3 (bf16) after 200 steps, measured on the same set-ups.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2005_12764_amd import lb
+from paper_2005_12764_amd import workloads as W
+from tests.helpers import oracle_params, state_errors
+
+pytestmark = pytest.mark.gpu
+
+TOL = {W.F64: 1e-12, W.F32: 1e-5, W.F16: 2e-4, W.BF16: 2e-3}
+
+
+def run_gpu(w, storage, steps, kernel=lb.KERNEL_AUTO, **over):
+    p = dict(w.params, storage=storage, kernel=kernel, **over)
+    with lb.Lattice(p) as L:
+        L.init(w.rho_r, w.rho_b, w.u)
+        L.step(steps)
+        return L.state(), L.kernel
+
+
+def run_oracle(w, steps, storage, **over):
+    p = dict(w.params, storage=storage, **over)
+    prm = oracle_params(p)
+    f = O.init(prm, w.rho_r, w.rho_b, w.u)
+    return O.step(prm, f, steps)
+
+
+def _parity(w, storage, steps, kernel=lb.KERNEL_AUTO, tol=None, **over):
+    f_gpu, used = run_gpu(w, storage, steps, kernel, **over)
+    f_ref = run_oracle(w, steps, storage, **over)
+    e = state_errors(f_gpu, f_ref)
+    tol = TOL[storage] if tol is None else tol
+    print("parity %s storage=%d kernel=%d steps=%d: %s" % (w.name, storage, used, steps, e), flush=True)
+    assert np.all(np.isfinite(f_gpu))
+    assert e["worst"] <= tol, e
+    return e
+
+
+# ---------------------------------------------------------- the 32^3 droplet
+
+@pytest.mark.parametrize("kernel", [lb.KERNEL_TWOPASS, lb.KERNEL_AUTO])
+@pytest.mark.parametrize("storage", [W.F64, W.F32])
+def test_single_droplet_200_steps(storage, kernel):
+    w = W.single_droplet(seed=0)
+    _parity(w, storage, 200, kernel)
+
+
+@pytest.mark.parametrize("storage", [W.F16, W.BF16])
+def test_single_droplet_16bit(storage):
+    w = W.single_droplet(seed=0)
+    _parity(w, storage, 200)
+
+
+# ----------------------------------------------------------- edge cases (F64)
+
+EDGE = [
+    ("tiny_periodic_1", (1, 1, 1), (0, 0, 0)),
+    ("tiny_periodic_4", (4, 4, 4), (0, 0, 0)),
+    ("tiny_walls", (3, 5, 2), (1, 1, 1)),
+    ("ragged_channel", (37, 29, 11), (0, 1, 1)),
+    ("ragged_periodic", (67, 13, 9), (0, 0, 0)),
+    ("walls_x", (19, 7, 70), (1, 0, 0)),
+]
+
+
+@pytest.mark.parametrize("name,n,bc", EDGE, ids=[e[0] for e in EDGE])
+@pytest.mark.parametrize("storage", [W.F64, W.F32])
+def test_edge_shapes_random_state(name, n, bc, storage):
+    nx, ny, nz = n
+    rr, rb, u = W.random_state(17, (nz, ny, nx))
+    p = W.base_params(nx, ny, nz, bc=bc, storage=storage, tau_r=0.7, tau_b=1.2, A=0.01,
+                      beta=0.7, nc_strength=0.03, nc_range=2, nc_hmin=1.5,
+                      body_force=(1e-5, -2e-6, 3e-6))
+    w = W.Workload(name, p, rr, rb, u)
+    _parity(w, storage, 12)
+
+
+@pytest.mark.parametrize("K,hmin", [(1, 1.0), (3, 2.0), (4, 2.5)])
+def test_near_contact_ranges(K, hmin):
+    w = W.two_droplets(n=(40, 24, 20), R=6, gap=2.0, A=0.01, nc_strength=0.03, nc_range=K,
+                       nc_hmin=hmin)
+    _parity(w, W.F64, 30)
+
+
+def test_crystal_channel_slice_f32():
+    # a short slab of the microfluidic-crystal channel: walls, force, near-contact
+    w = W.crystal_channel(seed=2, nx=88, ny=128, nz=64, steps=40)
+    _parity(w, W.F32, 40)
+
+
+# -------------------------------------------------------- moments and totals
+
+def test_moments_match_brute_force_sums_of_exported_state():
+    rr, rb, u = W.random_state(4, (4, 4, 4))
+    p = W.base_params(4, 4, 4, storage=W.F64, tau_r=0.8, tau_b=0.9, A=0.01)
+    with lb.Lattice(p) as L:
+        L.init(rr, rb, u).step(3)
+        f = L.state()
+        mr, mb, mj = L.moments()
+    c, _, _, _ = O.tables()
+    assert np.allclose(mr, f[0].sum(0), rtol=1e-14, atol=0)
+    assert np.allclose(mb, f[1].sum(0), rtol=1e-14, atol=0)
+    assert np.allclose(mj, np.einsum("kixyz,ia->axyz", f, c.astype(float)), rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("storage", [W.F64, W.F32, W.F16])
+def test_compensated_totals(storage):
+    # the totals are FP64 sums of the stored populations: compare with exact
+    # (fsum) sums of the exported state
+    w = W.single_droplet(seed=1, storage=storage)
+    with lb.Lattice(dict(w.params, storage=storage)) as L:
+        L.init(w.rho_r, w.rho_b).step(5)
+        t = L.totals()
+        f = L.state()
+        t2 = L.totals()
+    assert np.array_equal(t, t2)                               # deterministic
+    tot = t[:, 0] + t[:, 1]
+    c, _, _, _ = O.tables()
+    rr, rb = f[0].sum(0), f[1].sum(0)
+    j = np.einsum("kixyz,ia->axyz", f, c.astype(float))
+    assert math.isclose(tot[0], math.fsum(f[0].ravel()), rel_tol=1e-14)
+    assert math.isclose(tot[1], math.fsum(f[1].ravel()), rel_tol=1e-14)
+    for a in range(3):
+        assert abs(tot[2 + a] - math.fsum(j[a].ravel())) < 1e-12
+    ke = 0.5 * (j ** 2).sum(0) / (rr + rb)
+    assert math.isclose(tot[5], math.fsum(ke.ravel()), rel_tol=1e-9, abs_tol=1e-20)
+    assert tot[6] == 0.0
+
+
+def test_mass_conservation_f64_200_steps():
+    w = W.single_droplet(seed=0)
+    with lb.Lattice(dict(w.params, storage=W.F64)) as L:
+        L.init(w.rho_r, w.rho_b)
+        t0 = L.totals()
+        L.step(200)
+        t1 = L.totals()
+    m0, m1 = t0[:, 0] + t0[:, 1], t1[:, 0] + t1[:, 1]
+    assert abs(m1[0] / m0[0] - 1) < 1e-13 and abs(m1[1] / m0[1] - 1) < 1e-13
+    assert np.abs(m1[2:5]).max() < 1e-11                        # no forcing: momentum stays ~0
+
+
+# ------------------------------------------------------- state, determinism
+
+def test_state_roundtrip_and_checkpoint_resume():
+    w = W.single_droplet(seed=3)
+    p = dict(w.params, storage=W.F32)
+    with lb.Lattice(p) as A, lb.Lattice(p) as B:
+        A.init(w.rho_r, w.rho_b).step(20)
+        straight = A.state(np.float32)
+        B.init(w.rho_r, w.rho_b).step(10)
+        ck = B.save_raw()
+        B.step(3)                      # advance, then roll back to the checkpoint
+        B.load_raw(ck)
+        B.step(10)
+        assert np.array_equal(B.state(np.float32), straight)
+        # export -> import -> export is exact for raw storage
+        s = A.state(np.float64)
+        A.set_state(s)
+        assert np.array_equal(A.state(np.float64), s)
+
+
+@pytest.mark.parametrize("storage", [W.F32, W.F16])
+def test_run_twice_bitwise(storage):
+    w = W.two_droplets(n=(40, 24, 16), R=6, gap=2.0, A=0.01, nc_strength=0.03, nc_range=2)
+    a, _ = run_gpu(w, storage, 25)
+    b, _ = run_gpu(w, storage, 25)
+    assert np.array_equal(a, b)
+
+
+def test_device_tensors_and_torch_stream():
+    import torch
+    w = W.single_droplet(seed=5)
+    dev = torch.device("cuda:0")
+    rr = torch.from_numpy(w.rho_r).to(dev)
+    rb = torch.from_numpy(w.rho_b).to(dev)
+    stream = torch.cuda.current_stream()
+    p = dict(w.params, storage=W.F64)
+    with lb.Lattice(p, stream=stream) as L:
+        L.init(rr, rb).step(10)
+        out = torch.empty((2, 19) + w.shape, dtype=torch.float64, device=dev)
+        lb.lb_get_state(L.h, out)
+        torch.cuda.synchronize()
+        host = L.state()
+    assert np.array_equal(out.cpu().numpy(), host)
+    ref = run_oracle(w, 10, W.F64)
+    assert state_errors(host, ref)["worst"] < 1e-13
+
+
+def test_invalid_use_reports_errors():
+    p = W.base_params(8, 8, 8, storage=W.F32)
+    with lb.Lattice(p) as L:
+        with pytest.raises(lb.LbError) as e:
+            L.step(1)                                  # before init
+        assert e.value.code == lb.LB_ESTATE
+        bad = np.ones((8, 8, 8))
+        with pytest.raises(lb.LbError) as e:
+            L.init(bad, -bad)                          # negative density
+        assert e.value.code == lb.LB_EINVAL
