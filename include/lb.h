@@ -112,6 +112,14 @@ int lb_create(const lb_params* params, void* hip_stream, lb_t** out);
 int lb_init_fields(lb_t* h, const void* rho_r, const void* rho_b, const void* u, int32_t dtype,
                    int32_t on_device);
 
+/* Initial state from a droplet list instead of fields: phase field
+ * phi0(x) = max(background, max_j tanh((R_j - d_j(x))/width)) over droplets
+ * with d_j <= R_j + 6 width (d_j the distance to centre j, minimum image on
+ * periodic axes), rho_r = rho0 (1 + phi0)/2, rho_b = rho0 (1 - phi0)/2, u = 0;
+ * then as lb_init_fields.  centres: n x 3 (x, y, z) and radii: n, host memory. */
+int lb_init_droplets(lb_t* h, const double* centres, const double* radii, int32_t n, double width,
+                     double background, double rho0);
+
 /* Enqueue n >= 0 full steps (collide, then stream). */
 int lb_step(lb_t* h, int32_t n);
 
@@ -159,6 +167,61 @@ const char* lb_last_error(void);
 
 /* Bytes of device memory a lattice with these parameters holds. */
 int64_t lb_footprint_bytes(const lb_params* params);
+
+/* ------------------------------------------------------------------------
+ * Batched form: many independent lattices (jobs) of uneven sizes and
+ * parameters advanced together, one persistent kernel launch per pass over
+ * every active job's tiles, replayed as a captured HIP graph of steps.
+ * All jobs of a batch share one storage type.  Job populations live in one
+ * arena owned by the batch; admission fails with LB_ENOMEM when the arena has
+ * no room, so the arena size is the HBM budget.
+ * ------------------------------------------------------------------------ */
+typedef struct lb_batch_t lb_batch_t;
+
+/* max_jobs: slots; arena_bytes: device memory for job populations;
+ * storage: LB_STORE_*; graph_steps: steps per captured graph (even, >= 2).
+ * hip_stream NULL: the batch creates its own stream (graph capture cannot use
+ * the legacy default stream). */
+int lb_batch_create(int32_t max_jobs, int64_t arena_bytes, int32_t storage, int32_t graph_steps,
+                    void* hip_stream, lb_batch_t** out);
+
+/* Admit one job that will run `steps` steps: validates params (storage must
+ * equal the batch's; near-contact range at most 2), places it in the arena,
+ * writes its initial state f^eq(rho_k, u) (a 16-bit job also takes its first
+ * step here, from the raw FP32 initial state).  *slot gets its slot index.
+ * LB_ENOMEM when no slot or arena space is free.  Synchronises the stream. */
+int lb_batch_add(lb_batch_t* b, const lb_params* params, const void* rho_r, const void* rho_b,
+                 const void* u, int32_t dtype, int32_t on_device, int64_t steps, int32_t* slot);
+
+/* As lb_batch_add with the initial state of lb_init_droplets. */
+int lb_batch_add_droplets(lb_batch_t* b, const lb_params* params, const double* centres,
+                          const double* radii, int32_t n, double width, double background,
+                          double rho0, int64_t steps, int32_t* slot);
+
+/* Arena bytes one job with these parameters takes (-1 if invalid). */
+int64_t lb_batch_job_bytes(const lb_params* params);
+
+/* Remove a job and free its arena space (after its queued work). */
+int lb_batch_remove(lb_batch_t* b, int32_t slot);
+
+/* Advance the batch by n global steps: every job inside its step window
+ * takes a step each time (full multiples of graph_steps replay the captured
+ * graph; a remainder runs eagerly).  A job stops after its `steps` steps and
+ * keeps its final state until removed. */
+int lb_batch_step(lb_batch_t* b, int32_t n);
+
+/* Per-job moments and state export, as lb_moments / lb_get_state. */
+int lb_batch_moments(lb_batch_t* b, int32_t slot, void* rho_r, void* rho_b, void* mom,
+                     int32_t dtype, int32_t on_device, double totals[14]);
+int lb_batch_get_state(lb_batch_t* b, int32_t slot, void* f, int32_t dtype, int32_t on_device);
+
+/* Steps the job in `slot` has taken; -1 for an empty slot. */
+int64_t lb_batch_job_steps(const lb_batch_t* b, int32_t slot);
+
+/* Arena bytes still free (largest contiguous block). */
+int64_t lb_batch_free_bytes(const lb_batch_t* b);
+
+int lb_batch_destroy(lb_batch_t* b);
 
 #ifdef __cplusplus
 }

@@ -190,6 +190,10 @@ int lb_create(const lb_params* params, void* hip_stream, lb_t** out) {
     h->cd = make_coeffs<double>(h->p);
     h->cf = make_coeffs<float>(h->p);
     h->kernel = choose_kernel(h->p);
+    if (h->kernel < 0) {
+        delete h;
+        return fail(LB_EINVAL, "the fused kernel cannot hold this near-contact halo in LDS; use LB_KERNEL_TWOPASS");
+    }
     const size_t N = (size_t)h->g.N;
     const size_t pb = pop_bytes(h->p.storage, N);
     int rc = LB_OK;
@@ -250,6 +254,44 @@ int lb_init_fields(lb_t* h, const void* rho_r, const void* rho_b, const void* u,
         (void)hipStreamSynchronize(h->stream);
         (void)hipFree(scratch);
     }
+    if (rc) return rc;
+    h->initialised = true;
+    h->steps = 0;
+    return LB_OK;
+}
+
+int lb_init_droplets(lb_t* h, const double* centres, const double* radii, int32_t n, double width,
+                     double background, double rho0) {
+    if (!h) return fail(LB_EINVAL, "handle is NULL");
+    if (n < 0 || (n > 0 && (!centres || !radii))) return fail(LB_EINVAL, "bad droplet list");
+    if (!(width > 0.0) || !(rho0 > 0.0) || !(background >= -1.0 && background <= 1.0))
+        return fail(LB_EINVAL, "width and rho0 must be > 0, background in [-1, 1]");
+    for (int32_t j = 0; j < n; ++j)
+        if (!(radii[j] >= 0.0) || !std::isfinite(centres[3 * j] + centres[3 * j + 1] + centres[3 * j + 2]))
+            return fail(LB_EINVAL, "droplet radii must be >= 0 and centres finite");
+    const size_t N = (size_t)h->g.N;
+    const bool split = h->p.storage >= LB_STORE_F16;
+    if (split && !h->pending) {
+        int rc = check_hip(hipMalloc(&h->pending, pop_bytes(LB_STORE_F32, N)), "hipMalloc initial state");
+        if (rc) return rc;
+    }
+    double* tmp = nullptr;
+    const size_t bytes = (2 * N + 4 * (size_t)n + 4) * sizeof(double);
+    int rc = check_hip(hipMalloc((void**)&tmp, bytes), "hipMalloc droplet staging");
+    if (rc) return rc;
+    double* rr = tmp;
+    double* rb = tmp + N;
+    double* dc = tmp + 2 * N;
+    double* dr = dc + 3 * (size_t)n;
+    if (n) rc = check_hip(hipMemcpyAsync(dc, centres, 3 * sizeof(double) * n, hipMemcpyHostToDevice, h->stream), "H2D");
+    if (!rc && n) rc = check_hip(hipMemcpyAsync(dr, radii, sizeof(double) * n, hipMemcpyHostToDevice, h->stream), "H2D");
+    if (!rc) rc = launch_droplets(h->stream, h->g, dc, dr, n, width, background, rho0, rr, rb);
+    if (!rc) {
+        LatticeView v = view_of(h);
+        rc = launch_init(v, rr, rb, nullptr, LB_DTYPE_F64);
+    }
+    (void)hipStreamSynchronize(h->stream);
+    (void)hipFree(tmp);
     if (rc) return rc;
     h->initialised = true;
     h->steps = 0;

@@ -114,7 +114,10 @@ struct Half<__hip_bfloat16> {
     static __device__ __forceinline__ __hip_bfloat16 from_f(float v) { return __float2bfloat16(v); }
 };
 
-// 16-bit moment-split storage.  Per site, 8 FP32 values rec[8][N]: density,
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// 16-bit moment-split storage.  Per site, 8 FP32 values rec[N][8] (two
+// 16-byte vectors per site): density,
 // velocity (3), red fraction, recolouring vector (3) of the post-collision
 // state; per direction dev[19][N]: the total post-collision population minus
 // its equilibrium rho f^eq_unit(u), times `scale`, in 16 bits.  The red part
@@ -135,9 +138,10 @@ struct SplitPop {
         for (int i = 0; i < Q; ++i) {
             int d;
             const int src = pull_source(g, i, x, y, z, s, d);
-            const float rho = rec[src], ux = rec[N + src], uy = rec[2 * N + src],
-                        uz = rec[3 * N + src], xr = rec[4 * N + src], vx = rec[5 * N + src],
-                        vy = rec[6 * N + src], vz = rec[7 * N + src];
+            const f4 ra = *reinterpret_cast<const f4*>(rec + 8 * (size_t)src);
+            const f4 rb = *reinterpret_cast<const f4*>(rec + 8 * (size_t)src + 4);
+            const float rho = ra.x, ux = ra.y, uy = ra.z, uz = ra.w;
+            const float xr = rb.x, vx = rb.y, vy = rb.z, vz = rb.w;
             const float dv = Half<H>::to_f(dev[(size_t)d * N + src]) * inv_scale;
             // direction d is i, or its opposite after a bounce-back (same shell)
             const float sg = (d == i) ? 1.0f : -1.0f;
@@ -156,14 +160,10 @@ struct SplitPop {
     __device__ __forceinline__ void store(int s, const R (&fr)[Q], const R (&fb)[Q],
                                           const SiteTotals<R>& t) const {
         const float rho = float(t.rho), ux = float(t.ux), uy = float(t.uy), uz = float(t.uz);
-        __builtin_nontemporal_store(rho, &rec[s]);
-        __builtin_nontemporal_store(ux, &rec[N + s]);
-        __builtin_nontemporal_store(uy, &rec[2 * N + s]);
-        __builtin_nontemporal_store(uz, &rec[3 * N + s]);
-        __builtin_nontemporal_store(float(t.xr), &rec[4 * N + s]);
-        __builtin_nontemporal_store(float(t.vx), &rec[5 * N + s]);
-        __builtin_nontemporal_store(float(t.vy), &rec[6 * N + s]);
-        __builtin_nontemporal_store(float(t.vz), &rec[7 * N + s]);
+        const f4 ra = {rho, ux, uy, uz};
+        const f4 rb = {float(t.xr), float(t.vx), float(t.vy), float(t.vz)};
+        __builtin_nontemporal_store(ra, reinterpret_cast<f4*>(rec + 8 * (size_t)s));
+        __builtin_nontemporal_store(rb, reinterpret_cast<f4*>(rec + 8 * (size_t)s + 4));
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             const float fs = float(fr[i]) + float(fb[i]);
@@ -173,6 +173,26 @@ struct SplitPop {
     }
     static constexpr bool needs_totals = true;
 };
+
+// Minimum waves per SIMD the step kernels ask the compiler for, per storage.
+// The 16-bit decode keeps the 19 source records in flight (~190 VGPRs, two
+// waves per SIMD); asking for more waves makes the compiler spill, which
+// measured 3x slower, so no bound is imposed by default.
+#ifndef LB_SPLIT_WAVES
+#define LB_SPLIT_WAVES 1
+#endif
+template <typename S>
+struct Occupancy {
+    static constexpr int waves = 1;
+};
+template <typename H>
+struct Occupancy<SplitPop<H>> {
+    static constexpr int waves = LB_SPLIT_WAVES;
+};
+template <typename A, typename B>
+constexpr int waves_of() {
+    return Occupancy<A>::waves > Occupancy<B>::waves ? Occupancy<A>::waves : Occupancy<B>::waves;
+}
 
 // ---------------------------------------------------------------------------
 // Phase field and colour gradient.
@@ -243,7 +263,7 @@ __device__ __forceinline__ void near_contact(const Geom& g, const R* __restrict_
 
 // Pass 1: phi = (rho_r - rho_b)/rho of the post-streaming state.
 template <typename R, typename Src>
-__global__ __launch_bounds__(256) void phase_kernel(Geom g, Src src, R* __restrict__ phi) {
+__global__ __launch_bounds__(256, Occupancy<Src>::waves) void phase_kernel(Geom g, Src src, R* __restrict__ phi) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= g.N) return;
     int x, y, z;
@@ -261,7 +281,7 @@ __global__ __launch_bounds__(256) void phase_kernel(Geom g, Src src, R* __restri
 
 // Pass 2: pull, colour gradient, near-contact, collision, store.
 template <typename R, typename Src, typename Dst>
-__global__ __launch_bounds__(256) void collide_kernel(Geom g, Src src, Dst dst,
+__global__ __launch_bounds__(256, (waves_of<Src, Dst>())) void collide_kernel(Geom g, Src src, Dst dst,
                                                       const R* __restrict__ phi, Coeffs<R> c) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= g.N) return;
@@ -389,6 +409,35 @@ __global__ __launch_bounds__(256) void moments_kernel(Geom g, Src src, Out* rr_o
         j_out[N + s] = Out(jy);
         j_out[2 * N + s] = Out(jz);
     }
+}
+
+// Initial densities from a droplet list: phi0 = max(background,
+// max_j tanh((R_j - d_j)/width)) over droplets with d_j <= R_j + 6 width
+// (periodic minimum image on periodic axes), rho_r = rho0 (1 + phi0)/2,
+// rho_b = rho0 (1 - phi0)/2.
+__device__ __forceinline__ double min_image(double d, int n, int wall) {
+    return wall ? d : d - double(n) * rint(d / double(n));
+}
+
+static __global__ __launch_bounds__(256) void droplet_fields_kernel(Geom g, const double* __restrict__ cen,
+                                                                   const double* __restrict__ rad, int n,
+                                                                   double width, double background, double rho0,
+                                                                   double* __restrict__ rr, double* __restrict__ rb) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= g.N) return;
+    int x, y, z;
+    site_xyz(g, s, x, y, z);
+    double phi = background;
+    for (int j = 0; j < n; ++j) {
+        const double R = rad[j];
+        const double dx = min_image(double(x) - cen[3 * j], g.nx, g.wx);
+        const double dy = min_image(double(y) - cen[3 * j + 1], g.ny, g.wy);
+        const double dz = min_image(double(z) - cen[3 * j + 2], g.nz, g.wz);
+        const double r = sqrt(dx * dx + dy * dy + dz * dz);
+        if (r <= R + 6.0 * width) phi = fmax(phi, tanh((R - r) / width));
+    }
+    rr[s] = rho0 * (1.0 + phi) / 2.0;
+    rb[s] = rho0 * (1.0 - phi) / 2.0;
 }
 
 // ---------------------------------------------------------------------------

@@ -2,10 +2,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cmath>
 #include <string>
 #include <type_traits>
 
+#include "lb_fused.hpp"
 #include "lb_internal.hpp"
 
 namespace lbm {
@@ -53,6 +55,101 @@ int with_state(const LatticeView& v, Fn&& fn) {
     return set_error(LB_EINVAL, "unknown storage");
 }
 
+constexpr int kTX = 64;
+
+int max_lds_bytes() {
+    static int cached = -1;
+    if (cached < 0) {
+        int dev = 0, v = 0;
+        (void)hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+            v = 65536;
+        cached = std::min(v, 65536);
+    }
+    return cached;
+}
+
+int env_int(const char* name, int dflt) {
+    const char* e = std::getenv(name);
+    return (e && *e) ? std::atoi(e) : dflt;
+}
+
+// Halo of the fused kernel: the colour gradient needs one site, the
+// near-contact probe K more.
+int fused_halo(const lb_params& p) { return 1 + ((p.nc_strength > 0.0) ? p.nc_range : 0); }
+
+size_t real_size(const lb_params& p) { return p.storage == LB_STORE_F64 ? 8 : 4; }
+
+size_t fused_lds(const lb_params& p, int TY) {
+    const int H = fused_halo(p);
+    return (size_t)(2 * H + 1) * (TY + 2 * H) * (kTX + 2 * H) * real_size(p);
+}
+
+// Tile rows: the largest that keeps the phi ring within the LDS budget.
+int fused_rows(const lb_params& p) {
+    const int want = env_int("LB_FUSED_TY", 0);
+    if (want > 0) return fused_lds(p, want) <= (size_t)max_lds_bytes() ? want : 0;
+    for (int ty : {16, 8, 4, 2})
+        if (fused_lds(p, ty) <= (size_t)max_lds_bytes()) return ty;
+    return 0;
+}
+
+FusedShape fused_shape(const lb_params& p) {
+    FusedShape fs;
+    fs.TY = fused_rows(p);
+    fs.tiles_x = (p.nx + kTX - 1) / kTX;
+    fs.tiles_y = (p.ny + fs.TY - 1) / fs.TY;
+    const int tiles = fs.tiles_x * fs.tiles_y;
+    int tz = env_int("LB_FUSED_TZ", 0);
+    if (tz <= 0) {
+        // aim for >= 1024 workgroups, but keep chunks >= 4 * halo planes deep
+        const int H = fused_halo(p);
+        const int want_chunks = std::max(1, 1024 / std::max(1, tiles));
+        tz = std::max(4 * H, (p.nz + want_chunks - 1) / want_chunks);
+    }
+    fs.TZ = std::min(tz, p.nz);
+    fs.chunks = (p.nz + fs.TZ - 1) / fs.TZ;
+    fs.nblocks = tiles * fs.chunks;
+    return fs;
+}
+
+// z-marching tile kernel: phi_in == nullptr computes phi itself (single
+// pass), otherwise reads the phase pass's phi (collide pass of two-pass).
+template <typename R, typename Src, typename Dst, int H>
+int zmarch_h(const LatticeView& v, const Src& src, const Dst& dst, const Coeffs<R>& c, const R* phi_in) {
+    const FusedShape fs = fused_shape(*v.p);
+    const size_t lds = (size_t)(2 * H + 1) * (fs.TY + 2 * H) * (kTX + 2 * H) * sizeof(R);
+    hipLaunchKernelGGL((fused_kernel<R, Src, Dst, kTX, H>), dim3(fs.nblocks), dim3(kBlock), lds, v.stream, v.g, src,
+                       dst, c, fs, phi_in);
+    return launch_status(phi_in ? "collide pass" : "fused_kernel");
+}
+
+template <typename R, typename Src, typename Dst>
+int zmarch(const LatticeView& v, const Src& src, const Dst& dst, const Coeffs<R>& c, const R* phi_in) {
+    switch (fused_halo(*v.p)) {
+        case 1: return zmarch_h<R, Src, Dst, 1>(v, src, dst, c, phi_in);
+        case 2: return zmarch_h<R, Src, Dst, 2>(v, src, dst, c, phi_in);
+        case 3: return zmarch_h<R, Src, Dst, 3>(v, src, dst, c, phi_in);
+        case 4: return zmarch_h<R, Src, Dst, 4>(v, src, dst, c, phi_in);
+        case 5: return zmarch_h<R, Src, Dst, 5>(v, src, dst, c, phi_in);
+    }
+    return set_error(LB_EINVAL, "near-contact range outside the tile kernels' halo");
+}
+
+template <typename R, typename Src, typename Dst>
+int fused(const LatticeView& v, const Src& src, const Dst& dst, const Coeffs<R>& c, const StepEvents* t) {
+    if (t) {
+        (void)hipEventRecord(t->ev[0], v.stream);
+        (void)hipEventRecord(t->ev[1], v.stream);
+    }
+    int rc = zmarch<R>(v, src, dst, c, (const R*)nullptr);
+    if (t) (void)hipEventRecord(t->ev[2], v.stream);
+    return rc;
+}
+
+// Two passes: the phase pass writes phi; the collide pass z-marches tiles
+// with phi in an LDS ring (or, when the ring does not fit, reads phi from
+// global memory site by site).
 template <typename R, typename Src, typename Dst>
 int two_pass(const LatticeView& v, const Src& src, const Dst& dst, const Coeffs<R>& c, const StepEvents* t) {
     const unsigned grid = grid_for(v.g.N);
@@ -61,56 +158,63 @@ int two_pass(const LatticeView& v, const Src& src, const Dst& dst, const Coeffs<
     int rc = launch_status("phase_kernel");
     if (rc) return rc;
     if (t) (void)hipEventRecord(t->ev[1], v.stream);
-    hipLaunchKernelGGL((collide_kernel<R, Src, Dst>), dim3(grid), dim3(kBlock), 0, v.stream, v.g, src, dst,
-                       (const R*)v.phi, c);
-    rc = launch_status("collide_kernel");
+    if (fused_rows(*v.p) > 0 && env_int("LB_TWOPASS_SIMPLE", 0) == 0) {
+        rc = zmarch<R>(v, src, dst, c, (const R*)v.phi);
+    } else {
+        hipLaunchKernelGGL((collide_kernel<R, Src, Dst>), dim3(grid), dim3(kBlock), 0, v.stream, v.g, src, dst,
+                           (const R*)v.phi, c);
+        rc = launch_status("collide_kernel");
+    }
     if (t) (void)hipEventRecord(t->ev[2], v.stream);
     return rc;
+}
+
+template <typename R, typename Src, typename Dst>
+int step_with(const LatticeView& v, int kernel, const Src& src, const Dst& dst, const Coeffs<R>& c,
+              const StepEvents* t) {
+    if (kernel == LB_KERNEL_FUSED) return fused<R>(v, src, dst, c, t);
+    return two_pass<R>(v, src, dst, c, t);
 }
 
 }  // namespace
 
 int choose_kernel(const lb_params& p) {
-    (void)p;
-    return LB_KERNEL_TWOPASS;
+    const bool fits = fused_rows(p) > 0;
+    if (p.kernel == LB_KERNEL_TWOPASS) return LB_KERNEL_TWOPASS;
+    if (p.kernel == LB_KERNEL_FUSED) return fits ? LB_KERNEL_FUSED : -1;
+    // automatic: the fused kernel once a tile row is mostly interior sites
+    const double N = double(p.nx) * p.ny * p.nz;
+    return (fits && p.nx >= 32 && N >= 32768.0) ? LB_KERNEL_FUSED : LB_KERNEL_TWOPASS;
+}
+
+// Source/destination storage pairs a step may combine: same storage, or the
+// raw FP32 initial state of a 16-bit lattice into its moment-split storage.
+template <typename Src, typename Dst>
+struct StepPair : std::false_type {};
+template <typename T>
+struct StepPair<RawPop<T>, RawPop<T>> : std::true_type {};
+template <typename H>
+struct StepPair<RawPop<float>, SplitPop<H>> : std::true_type {};
+template <typename H>
+struct StepPair<SplitPop<H>, SplitPop<H>> : std::true_type {};
+
+template <typename Dst>
+int step_into(const LatticeView& v, int kernel, const Dst& dst, const StepEvents* t) {
+    return with_state(v, [&](auto rt, auto src, const auto& c) {
+        using R = decltype(rt);
+        using S = decltype(src);
+        if constexpr (StepPair<S, Dst>::value) return step_with<R>(v, kernel, src, dst, c, t);
+        return set_error(LB_EINVAL, "storage/compute mismatch");
+    });
 }
 
 int launch_step(const LatticeView& v, int kernel, const StepEvents* t) {
-    (void)kernel;
     const size_t N = (size_t)v.g.N;
     switch (v.p->storage) {
-        case LB_STORE_F64: {
-            RawPop<double> dst{(double*)v.nxt, N};
-            return with_state(v, [&](auto rt, auto src, const auto& c) {
-                using R = decltype(rt);
-                if constexpr (std::is_same<R, double>::value) return two_pass<R>(v, src, dst, c, t);
-                return set_error(LB_EINVAL, "storage/compute mismatch");
-            });
-        }
-        case LB_STORE_F32: {
-            RawPop<float> dst{(float*)v.nxt, N};
-            return with_state(v, [&](auto rt, auto src, const auto& c) {
-                using R = decltype(rt);
-                if constexpr (std::is_same<R, float>::value) return two_pass<R>(v, src, dst, c, t);
-                return set_error(LB_EINVAL, "storage/compute mismatch");
-            });
-        }
-        case LB_STORE_F16: {
-            auto dst = split_view<__half>(v.nxt, N, v.p->scale_log2);
-            return with_state(v, [&](auto rt, auto src, const auto& c) {
-                using R = decltype(rt);
-                if constexpr (std::is_same<R, float>::value) return two_pass<R>(v, src, dst, c, t);
-                return set_error(LB_EINVAL, "storage/compute mismatch");
-            });
-        }
-        case LB_STORE_BF16: {
-            auto dst = split_view<__hip_bfloat16>(v.nxt, N, v.p->scale_log2);
-            return with_state(v, [&](auto rt, auto src, const auto& c) {
-                using R = decltype(rt);
-                if constexpr (std::is_same<R, float>::value) return two_pass<R>(v, src, dst, c, t);
-                return set_error(LB_EINVAL, "storage/compute mismatch");
-            });
-        }
+        case LB_STORE_F64: return step_into(v, kernel, RawPop<double>{(double*)v.nxt, N}, t);
+        case LB_STORE_F32: return step_into(v, kernel, RawPop<float>{(float*)v.nxt, N}, t);
+        case LB_STORE_F16: return step_into(v, kernel, split_view<__half>(v.nxt, N, v.p->scale_log2), t);
+        case LB_STORE_BF16: return step_into(v, kernel, split_view<__hip_bfloat16>(v.nxt, N, v.p->scale_log2), t);
     }
     return set_error(LB_EINVAL, "unknown storage");
 }
@@ -179,6 +283,13 @@ int launch_moments(const LatticeView& v, void* rr, void* rb, void* j, int dtype)
                                (float*)rr, (float*)rb, (float*)j);
         return launch_status("moments_kernel");
     });
+}
+
+int launch_droplets(hipStream_t st, const Geom& g, const double* cen, const double* rad, int n, double width,
+                    double background, double rho0, double* rr, double* rb) {
+    hipLaunchKernelGGL(droplet_fields_kernel, dim3(grid_for(g.N)), dim3(kBlock), 0, st, g, cen, rad, n, width,
+                       background, rho0, rr, rb);
+    return launch_status("droplet_fields_kernel");
 }
 
 int launch_totals(const LatticeView& v, Neu* partial, double* dtot) {

@@ -104,7 +104,11 @@ def lib():
         "lb_last_error": ([], ctypes.c_char_p),
         "lb_footprint_bytes": ([pp], i64),
         "lb_batch_create": ([i32, i64, i32, i32, vp, ctypes.POINTER(vp)], i32),
-        "lb_batch_add": ([vp, pp, vp, vp, vp, i32, i32, ctypes.POINTER(i32)], i32),
+        "lb_batch_add": ([vp, pp, vp, vp, vp, i32, i32, i64, ctypes.POINTER(i32)], i32),
+        "lb_batch_add_droplets": ([vp, pp, dp, dp, i32, ctypes.c_double, ctypes.c_double,
+                                   ctypes.c_double, i64, ctypes.POINTER(i32)], i32),
+        "lb_batch_job_bytes": ([pp], i64),
+        "lb_init_droplets": ([vp, dp, dp, i32, ctypes.c_double, ctypes.c_double, ctypes.c_double], i32),
         "lb_batch_remove": ([vp, i32], i32),
         "lb_batch_step": ([vp, i32], i32),
         "lb_batch_moments": ([vp, i32, vp, vp, vp, i32, i32, dp], i32),
@@ -177,6 +181,20 @@ def lb_init_fields(h, rho_r, rho_b, u=None) -> None:
     _check(lib().lb_init_fields(h, pr, pb, pu, code, dev))
 
 
+def _droplets(centres, radii):
+    c = np.ascontiguousarray(np.asarray(centres, dtype=np.float64).reshape(-1, 3))
+    r = np.ascontiguousarray(np.asarray(radii, dtype=np.float64).reshape(-1))
+    if len(c) != len(r):
+        raise ValueError("centres and radii differ in length")
+    dp = ctypes.POINTER(ctypes.c_double)
+    return c, r, c.ctypes.data_as(dp), r.ctypes.data_as(dp)
+
+
+def lb_init_droplets(h, centres, radii, width=2.0, background=-1.0, rho0=1.0) -> None:
+    c, r, pc, pr = _droplets(centres, radii)
+    _check(lib().lb_init_droplets(h, pc, pr, len(r), float(width), float(background), float(rho0)))
+
+
 def lb_step(h, n: int = 1) -> None:
     _check(lib().lb_step(h, int(n)))
 
@@ -241,6 +259,99 @@ def lb_footprint_bytes(params: dict) -> int:
 
 
 # ----------------------------------------------------------------------------
+# Batched form
+# ----------------------------------------------------------------------------
+
+def lb_batch_job_bytes(params: dict) -> int:
+    prm = make_params(params)
+    return int(lib().lb_batch_job_bytes(ctypes.byref(prm)))
+
+
+class Batch:
+    """Many independent lattices advanced together by the batched step."""
+
+    def __init__(self, max_jobs: int, arena_bytes: int, storage: int = F16, graph_steps: int = 50,
+                 stream=None):
+        self.storage = int(storage)
+        self.h = ctypes.c_void_p()
+        _check(lib().lb_batch_create(int(max_jobs), int(arena_bytes), self.storage, int(graph_steps),
+                                     _stream_ptr(stream), ctypes.byref(self.h)))
+        self.shapes = {}
+
+    def add(self, params: dict, rho_r, rho_b, u=None, steps: int = 0) -> int:
+        prm = make_params(dict(params, storage=self.storage))
+        pr, dev, code, k1 = _arg(rho_r)
+        pb, _, _, k2 = _arg(rho_b, code)
+        pu, _, _, k3 = _arg(u, code)
+        slot = ctypes.c_int32()
+        _check(lib().lb_batch_add(self.h, ctypes.byref(prm), pr, pb, pu, code, dev, int(steps),
+                                  ctypes.byref(slot)))
+        self.shapes[slot.value] = (prm.nz, prm.ny, prm.nx)
+        return slot.value
+
+    def add_droplets(self, params: dict, centres, radii, steps: int, width=2.0, background=-1.0,
+                     rho0=1.0) -> int:
+        prm = make_params(dict(params, storage=self.storage))
+        c, r, pc, pr = _droplets(centres, radii)
+        slot = ctypes.c_int32()
+        _check(lib().lb_batch_add_droplets(self.h, ctypes.byref(prm), pc, pr, len(r), float(width),
+                                           float(background), float(rho0), int(steps),
+                                           ctypes.byref(slot)))
+        self.shapes[slot.value] = (prm.nz, prm.ny, prm.nx)
+        return slot.value
+
+    def remove(self, slot: int) -> None:
+        _check(lib().lb_batch_remove(self.h, int(slot)))
+        self.shapes.pop(slot, None)
+
+    def step(self, n: int) -> None:
+        _check(lib().lb_batch_step(self.h, int(n)))
+
+    def job_steps(self, slot: int) -> int:
+        return int(lib().lb_batch_job_steps(self.h, int(slot)))
+
+    def free_bytes(self) -> int:
+        return int(lib().lb_batch_free_bytes(self.h))
+
+    def totals(self, slot: int) -> np.ndarray:
+        tot = (ctypes.c_double * 14)()
+        _check(lib().lb_batch_moments(self.h, int(slot), None, None, None, DTYPE_F64, 0,
+                                      ctypes.cast(tot, ctypes.POINTER(ctypes.c_double))))
+        return np.array(tot[:], dtype=np.float64).reshape(7, 2)
+
+    def moments(self, slot: int):
+        shape = self.shapes[slot]
+        rr, rb, j = np.empty(shape), np.empty(shape), np.empty((3,) + shape)
+        vp = ctypes.c_void_p
+        _check(lib().lb_batch_moments(self.h, int(slot), vp(rr.ctypes.data), vp(rb.ctypes.data),
+                                      vp(j.ctypes.data), DTYPE_F64, 0, None))
+        return rr, rb, j
+
+    def state(self, slot: int, dtype=np.float64) -> np.ndarray:
+        out = np.empty((2, Q) + self.shapes[slot], dtype=dtype)
+        code = DTYPE_F64 if out.dtype == np.float64 else DTYPE_F32
+        _check(lib().lb_batch_get_state(self.h, int(slot), ctypes.c_void_p(out.ctypes.data), code, 0))
+        return out
+
+    def close(self):
+        if self.h is not None and self.h.value:
+            _check(lib().lb_batch_destroy(self.h))
+        self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ----------------------------------------------------------------------------
 # Convenience wrapper
 # ----------------------------------------------------------------------------
 
@@ -256,6 +367,10 @@ class Lattice:
 
     def init(self, rho_r, rho_b, u=None):
         lb_init_fields(self.h, rho_r, rho_b, u)
+        return self
+
+    def init_droplets(self, centres, radii, width=2.0, background=-1.0, rho0=1.0):
+        lb_init_droplets(self.h, centres, radii, width, background, rho0)
         return self
 
     def step(self, n: int = 1):

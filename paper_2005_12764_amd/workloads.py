@@ -69,8 +69,10 @@ def _axis_dist(coord: np.ndarray, c: float, n: int, periodic: bool) -> np.ndarra
 
 def droplet_phase(shape, centres, radii, bc=(0, 0, 0), width: float = 2.0,
                   background: float = -1.0) -> np.ndarray:
-    """phi0 = max_j tanh((R_j - d_j)/width); only a box around each droplet
-    is touched, so many droplets on a big lattice stay cheap."""
+    """phi0 = max(background, max_j tanh((R_j - d_j)/width)) over droplets
+    with d_j <= R_j + 6 width (the library's droplet initialiser uses the same
+    rule); only a box around each droplet is touched, so many droplets on a
+    big lattice stay cheap."""
     nz, ny, nx = shape
     n = (nx, ny, nz)
     phi = np.full(shape, background, dtype=np.float64)
@@ -94,7 +96,7 @@ def droplet_phase(shape, centres, radii, bc=(0, 0, 0), width: float = 2.0,
             continue
         dx, dy, dz = dist
         r = np.sqrt(dz[:, None, None] ** 2 + dy[None, :, None] ** 2 + dx[None, None, :] ** 2)
-        val = np.tanh((R - r) / width)
+        val = np.where(r <= R + 6 * width, np.tanh((R - r) / width), background)
         sub = np.ix_(idx[2], idx[1], idx[0])
         phi[sub] = np.maximum(phi[sub], val)
     return phi
@@ -137,7 +139,7 @@ def rsa_place(rng, n, radii, gap=1.0, bc=(0, 0, 0), attempts=10**6, batch=512):
     return placed_c, placed_r
 
 
-def emulsion(rng, n, phi_v, rmin, rmax, bc=(0, 0, 0), gap=1.0):
+def emulsion(rng, n, phi_v, rmin, rmax, bc=(0, 0, 0), gap=1.0, attempts=10**6):
     """Random emulsion of non-overlapping droplets at volume fraction phi_v.
     Radii are U[rmin, rmax]; droplets are drawn until their volume reaches
     phi_v of the box, then placed by RSA.  If RSA cannot reach the target
@@ -150,7 +152,7 @@ def emulsion(rng, n, phi_v, rmin, rmax, bc=(0, 0, 0), gap=1.0):
         R = rng.uniform(rmin, rmax)
         radii.append(R)
         vol += 4.0 / 3.0 * math.pi * R ** 3
-    centres, placed = rsa_place(rng, n, radii, gap=gap, bc=bc)
+    centres, placed = rsa_place(rng, n, radii, gap=gap, bc=bc, attempts=attempts)
     achieved = float((4.0 / 3.0 * math.pi * placed ** 3).sum() / V)
     inflate = 1.0
     if achieved < 0.98 * phi_v and achieved > 0:
@@ -244,11 +246,25 @@ class Job:
     steps: int
     seed: int
 
-    def workload(self, storage=F16) -> Workload:
+    def params(self, storage=F16) -> dict:
+        n = self.side
+        return base_params(n, n, n, storage=storage, tau_r=self.tau, tau_b=self.tau, A=self.A,
+                           beta=0.7, nc_strength=self.nc_strength, nc_range=2, nc_hmin=2.0)
+
+    def droplets(self):
+        """Droplet list of the job's emulsion (RSA with a bounded number of
+        draws per droplet, radii U[6, min(12, side/4)])."""
         rng = np.random.default_rng(self.seed)
         n = self.side
-        rmax = min(12.0, n / 4.0)
-        cen, rad, info = emulsion(rng, (n, n, n), self.phi_v, 6.0, rmax)
+        return emulsion(rng, (n, n, n), self.phi_v, 6.0, min(12.0, n / 4.0), attempts=1024)
+
+    @property
+    def sites(self) -> int:
+        return self.side ** 3
+
+    def workload(self, storage=F16) -> Workload:
+        n = self.side
+        cen, rad, info = self.droplets()
         phi0 = droplet_phase((n, n, n), cen, rad)
         rr, rb = split_components(phi0, 1.0)
         p = base_params(n, n, n, storage=storage, tau_r=self.tau, tau_b=self.tau, A=self.A,

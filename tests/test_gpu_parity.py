@@ -52,17 +52,18 @@ def _parity(w, storage, steps, kernel=lb.KERNEL_AUTO, tol=None, **over):
 
 # ---------------------------------------------------------- the 32^3 droplet
 
-@pytest.mark.parametrize("kernel", [lb.KERNEL_TWOPASS, lb.KERNEL_AUTO])
+@pytest.mark.parametrize("kernel", [lb.KERNEL_TWOPASS, lb.KERNEL_FUSED])
 @pytest.mark.parametrize("storage", [W.F64, W.F32])
 def test_single_droplet_200_steps(storage, kernel):
     w = W.single_droplet(seed=0)
     _parity(w, storage, 200, kernel)
 
 
+@pytest.mark.parametrize("kernel", [lb.KERNEL_TWOPASS, lb.KERNEL_FUSED])
 @pytest.mark.parametrize("storage", [W.F16, W.BF16])
-def test_single_droplet_16bit(storage):
+def test_single_droplet_16bit(storage, kernel):
     w = W.single_droplet(seed=0)
-    _parity(w, storage, 200)
+    _parity(w, storage, 200, kernel)
 
 
 # ----------------------------------------------------------- edge cases (F64)
@@ -78,28 +79,38 @@ EDGE = [
 
 
 @pytest.mark.parametrize("name,n,bc", EDGE, ids=[e[0] for e in EDGE])
+@pytest.mark.parametrize("kernel", [lb.KERNEL_TWOPASS, lb.KERNEL_FUSED])
 @pytest.mark.parametrize("storage", [W.F64, W.F32])
-def test_edge_shapes_random_state(name, n, bc, storage):
+def test_edge_shapes_random_state(name, n, bc, storage, kernel):
     nx, ny, nz = n
     rr, rb, u = W.random_state(17, (nz, ny, nx))
     p = W.base_params(nx, ny, nz, bc=bc, storage=storage, tau_r=0.7, tau_b=1.2, A=0.01,
                       beta=0.7, nc_strength=0.03, nc_range=2, nc_hmin=1.5,
                       body_force=(1e-5, -2e-6, 3e-6))
     w = W.Workload(name, p, rr, rb, u)
-    _parity(w, storage, 12)
+    _parity(w, storage, 12, kernel)
 
 
-@pytest.mark.parametrize("K,hmin", [(1, 1.0), (3, 2.0), (4, 2.5)])
-def test_near_contact_ranges(K, hmin):
+@pytest.mark.parametrize("kernel", [lb.KERNEL_TWOPASS, lb.KERNEL_FUSED])
+@pytest.mark.parametrize("K,hmin", [(1, 1.0), (2, 2.0), (3, 2.0), (4, 2.5)])
+def test_near_contact_ranges(K, hmin, kernel):
     w = W.two_droplets(n=(40, 24, 20), R=6, gap=2.0, A=0.01, nc_strength=0.03, nc_range=K,
                        nc_hmin=hmin)
-    _parity(w, W.F64, 30)
+    _parity(w, W.F32 if kernel == lb.KERNEL_FUSED and K == 4 else W.F64, 30, kernel)
+
+
+@pytest.mark.parametrize("bc", [(0, 1, 1), (1, 1, 1), (0, 0, 1)])
+def test_fused_walls_and_near_contact(bc):
+    w = W.two_droplets(n=(70, 21, 19), R=6, gap=2.0, A=0.01, nc_strength=0.03, nc_range=2)
+    w.params["bc"] = bc
+    w.params["body_force"] = (2e-6, 1e-6, -1e-6)
+    _parity(w, W.F64, 25, lb.KERNEL_FUSED)
 
 
 def test_crystal_channel_slice_f32():
     # a short slab of the microfluidic-crystal channel: walls, force, near-contact
     w = W.crystal_channel(seed=2, nx=88, ny=128, nz=64, steps=40)
-    _parity(w, W.F32, 40)
+    _parity(w, W.F32, 40, lb.KERNEL_FUSED)
 
 
 # -------------------------------------------------------- moments and totals
