@@ -60,6 +60,130 @@ def gpu_variant(w, storage, steps, warmup, stream, kernel=0):
         L.close()
 
 
+def copy_bandwidth(stream, gib=2.0, reps=10):
+    """Achievable HBM bandwidth of a plain device-to-device copy (read +
+    write bytes per second), the practical ceiling next to the 8 TB/s peak."""
+    import torch
+    n = int(gib * 2 ** 30) // 4
+    a = torch.empty(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(reps):
+        b.copy_(a)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * n * 4 / (ms * 1e-3) / 1e9
+
+
+def serving(reqs, prep, rate, steps, budget_gb):
+    import torch
+    from paper_2005_12764_amd import serve as S
+    from paper_2005_12764_amd import workloads as W
+    sstream = torch.cuda.Stream()
+    be = S.GpuBackend(int(budget_gb * 2 ** 30), max_jobs=512, storage=W.F16, chunk=50, stream=sstream)
+    with torch.cuda.stream(sstream):
+        rep = S.Server(be, chunk=50).run(reqs)
+    be.close()
+    out = rep.summary()
+    out.update(storage="f16", rate_jobs_per_s=rate, steps_per_job=steps, budget_gb=budget_gb,
+               request_prep_s=round(prep, 2))
+    return out
+
+
+def structure_factor(phi):
+    """Shell-averaged |FFT(phi - <phi>)|^2 (torch FFT of a device field):
+    returns (k, S(k)), the first moment k1 and the peak height."""
+    import torch
+    f = torch.fft.fftn(phi - phi.mean())
+    p = (f.real ** 2 + f.imag ** 2)
+    n = phi.shape[0]
+    k1d = torch.fft.fftfreq(n, d=1.0 / n).to(phi.device)
+    kz, ky, kx = torch.meshgrid(k1d, k1d, k1d, indexing="ij")
+    kk = torch.sqrt(kx ** 2 + ky ** 2 + kz ** 2).round().long().flatten()
+    nb = n // 2
+    m = kk <= nb
+    S = torch.zeros(nb + 1, dtype=torch.float64, device=phi.device).index_add_(0, kk[m], p.flatten()[m].double())
+    cnt = torch.zeros(nb + 1, dtype=torch.float64, device=phi.device).index_add_(
+        0, kk[m], torch.ones_like(p.flatten()[m], dtype=torch.float64))
+    S = (S / cnt.clamp(min=1)).cpu().numpy()
+    k = np.arange(nb + 1) * 2 * np.pi / n
+    k1 = float((k[1:] * S[1:]).sum() / S[1:].sum())
+    return k, S, k1, float(S[1:].max())
+
+
+def config_c3(args, stream):
+    """Microfluidic-crystal channel: FP32 and 16-bit storage against FP64."""
+    from paper_2005_12764_amd import lb
+    from paper_2005_12764_amd import workloads as W
+    from tests.helpers import state_errors
+    import torch
+    w = W.crystal_channel(seed=0, steps=args.c_steps or 2000)
+    res, states = {}, {}
+    for name, st in (("f64", 0), ("f32", 1), ("f16", 2), ("bf16", 3)):
+        with lb.Lattice(dict(w.params, storage=st), stream=stream) as L:
+            L.init(w.rho_r, w.rho_b)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            L.step(w.steps)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            states[name] = L.state()
+        res[name] = {"mlups": round(w.sites * w.steps / dt / 1e6, 1)}
+        log("c3 %s: %.0f MLUPS" % (name, res[name]["mlups"]))
+    for name in ("f32", "f16", "bf16"):
+        e = state_errors(states[name], states["f64"])
+        res[name]["err_vs_f64"] = {k: float("%.3e" % v) for k, v in e.items()}
+    return {"config": "microfluidic crystal channel 512x128x64, walls y/z, force 1e-6, 138 droplets R=10",
+            "steps": w.steps, "results": res}
+
+
+def config_c4(args, stream):
+    """Spinodal decomposition: structure factor of 16-bit storage vs FP32."""
+    from paper_2005_12764_amd import lb
+    from paper_2005_12764_amd import workloads as W
+    import torch
+    n = args.c4_n
+    w = W.spinodal(seed=0, n=n)
+    marks = [m for m in (1000, 2000, 5000) if m <= (args.c_steps or 5000)]
+    res = {}
+    for name, st in (("f32", 1), ("f16", 2), ("bf16", 3)):
+        out = {}
+        with lb.Lattice(dict(w.params, storage=st), stream=stream) as L:
+            L.init(w.rho_r, w.rho_b)
+            done, busy = 0, 0.0
+            rr = torch.empty(w.shape, dtype=torch.float32, device="cuda")
+            rb = torch.empty_like(rr)
+            for m in marks:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                L.step(m - done)
+                torch.cuda.synchronize()
+                busy += time.perf_counter() - t0
+                done = m
+                lb.lb_moments(L.h, rr, rb, None)
+                torch.cuda.synchronize()
+                phi = ((rr - rb) / (rr + rb)).double()
+                _, S, k1, peak = structure_factor(phi)
+                out[m] = {"k1": k1, "peak": peak}
+        res[name] = {"mlups": round(w.sites * done / busy / 1e6, 1), "S": out}
+        log("c4 %s: %.0f MLUPS %s" % (name, res[name]["mlups"], out))
+    for name in ("f16", "bf16"):
+        for m in marks:
+            a, b = res[name]["S"][m], res["f32"]["S"][m]
+            a["k1_rel_err"] = abs(a["k1"] / b["k1"] - 1)
+            a["peak_rel_err"] = abs(a["peak"] / b["peak"] - 1)
+    return {"config": "spinodal %d^3 50/50, noise 0.01, tau 1, A 0.01, near-contact 0.03 over 2 sites" % n,
+            "steps": marks[-1], "results": res}
+
+
 def cpu_baseline(w, steps):
     from oracle import oracle as O
     from tests.helpers import oracle_params
@@ -84,7 +208,13 @@ def main():
     ap.add_argument("--variants", default="f32,f16,bf16")
     ap.add_argument("--kernel", type=int, default=0, help="0 auto, 1 two-pass, 2 fused")
     ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--serve-jobs", type=int, default=200, help="jobs of the serving leg (0 = skip)")
+    ap.add_argument("--serve-rate", type=float, default=40.0)
+    ap.add_argument("--serve-steps", type=int, default=500)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--config", default="c2", help="c2 (headline), c3 (crystal channel), c4 (spinodal)")
+    ap.add_argument("--c-steps", type=int, default=0, help="steps of the c3/c4 runs (0 = the config's)")
+    ap.add_argument("--c4-n", type=int, default=384)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -92,9 +222,27 @@ def main():
               "(the domain decomposition is a design note); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
-    import torch
     from paper_2005_12764_amd import workloads as W
 
+    if args.config in ("c3", "c4"):
+        import torch
+        torch.cuda.set_device(0)
+        stream = torch.cuda.current_stream()
+        out = config_c3(args, stream) if args.config == "c3" else config_c4(args, stream)
+        print(json.dumps(out), flush=True)
+        return
+
+    # the serving leg's requests (droplet lists) are built by worker
+    # processes before this process touches the GPU
+    reqs, prep = None, 0.0
+    if args.serve_jobs > 0:
+        from paper_2005_12764_amd import serve as S
+        t0 = time.perf_counter()
+        reqs = S.make_requests(args.serve_jobs, seed=0, rate=args.serve_rate, steps=args.serve_steps)
+        prep = time.perf_counter() - t0
+        log("serving: %d requests prepared in %.1fs" % (len(reqs), prep))
+
+    import torch
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     t0 = time.perf_counter()
@@ -124,6 +272,16 @@ def main():
             "kernel": "collide_kernel" if head["kernel"] == 1 else "fused_kernel",
             "algo_bytes_per_site": ALGO_BYTES[st], "sites_per_launch": w.sites,
             "kernel_ms": round(dom_ms, 4)}
+
+    copy_gbs = copy_bandwidth(stream)
+    log("device copy: %.0f GB/s (read + write)" % copy_gbs)
+    roof["copy_gbs"] = round(copy_gbs, 1)
+    roof["frac_of_copy"] = round(achieved / copy_gbs, 4)
+
+    serve_out = None
+    if args.serve_jobs > 0:
+        serve_out = serving(reqs, prep, args.serve_rate, args.serve_steps, 0.8 * 288)
+        log("serving: %s" % serve_out)
 
     cpu = None
     if not args.no_cpu:
@@ -155,6 +313,7 @@ def main():
                          "pass_ms": [round(x, 4) for x in v["pass_ms"]],
                          "finite": v["finite"]} for k, v in results.items()},
         "roofline": roof,
+        "serving": serve_out,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -95,6 +95,13 @@ typedef struct {
                                <= 0 selects 1e-12 (F64) or 1e-6 (other storage) */
     double g_iface;         /* |G| threshold of interface sites for the near-contact
                                probe; <= 0 selects 0.05 */
+    double wall_velocity[6][3]; /* velocity of each wall face, faces -x,+x,-y,+y,-z,+z
+                               (used on wall axes only; zero = resting walls).  A
+                               population reflected by a moving face gains
+                               2 w_i (c_i . U)/c_s^2 (reference density 1), shared
+                               between the components by the reflecting site's
+                               rho_k/rho; edges get the sum of both faces' terms.
+                               The sheared channel of Sec. 5 slides two walls at +-U. */
 } lb_params;
 
 /* Create a lattice on the current HIP device.  Allocates the two population

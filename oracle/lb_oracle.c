@@ -48,7 +48,16 @@
  *   6 tau_r, 7 tau_b, 8 A (surface tension), 9 beta (recolouring),
  *   10 nc_strength, 11 nc_range K, 12 nc_hmin, 13..15 body force density,
  *   16 eps_g (|G| below which n = 0), 17 g_iface (interface threshold of the
- *   near-contact probe).
+ *   near-contact probe), 18..35 wall velocities of the six faces in the order
+ *   -x, +x, -y, +y, -z, +z (3 components each; used on wall axes only).
+ *
+ * Moving walls (the sheared channel of Sec. 5 has walls sliding at +-U): a
+ * population reflected by a wall face moving with velocity U gains
+ * 2 w_i rho_w (c_i . U)/c_s^2 with rho_w = 1, c_i its direction after the
+ * reflection, shared between the components in the proportion rho_k/rho of
+ * the reflecting site (its post-collision state), so a tangentially sliding
+ * wall leaves every component's mass unchanged.  A population crossing two
+ * wall faces (an edge) gets the sum of both faces' terms.
  */
 #include <math.h>
 #include <stdint.h>
@@ -90,6 +99,8 @@ typedef struct {
     double nc_hmin;
     double force[3];
     double eps_g, g_iface;
+    double uwall[6][3];
+    int moving;
 } prm_t;
 
 static prm_t unpack(const double *p) {
@@ -108,6 +119,12 @@ static prm_t unpack(const double *p) {
     q.nc_hmin = p[12];
     q.eps_g = p[16];
     q.g_iface = p[17];
+    q.moving = 0;
+    for (int f = 0; f < 6; ++f)
+        for (int a = 0; a < 3; ++a) {
+            q.uwall[f][a] = p[18 + 3 * f + a];
+            if (q.uwall[f][a] != 0.0 && q.bc[f / 2]) q.moving = 1;
+        }
     return q;
 }
 
@@ -429,7 +446,8 @@ void orc_collide(const double *p, const double *f, double *fpost, double *phi_ou
 
 /* Streaming: f^k_i(x + c_i) <- fpost^k_i(x).  A population whose target lies
  * beyond a wall on any wall axis is reflected back to its own site into the
- * opposite direction (halfway bounce-back); periodic axes wrap. */
+ * opposite direction (halfway bounce-back), plus the moving-wall term of every
+ * wall face it crosses; periodic axes wrap. */
 void orc_stream(const double *p, const double *fpost, double *f) {
     init_tables();
     prm_t q = unpack(p);
@@ -438,19 +456,35 @@ void orc_stream(const double *p, const double *fpost, double *f) {
     for (long long s = 0; s < (long long)N; ++s) {
         int x0[3];
         coords(&q, (size_t)s, &x0[0], &x0[1], &x0[2]);
+        double xr = 0.0; /* red fraction of the site, for moving-wall terms */
+        if (q.moving) {
+            double a = 0.0, b = 0.0;
+            for (int i = 0; i < Q; ++i) {
+                a += fpost[(size_t)i * N + s];
+                b += fpost[(size_t)(Q + i) * N + s];
+            }
+            xr = a / (a + b);
+        }
         for (int i = 0; i < Q; ++i) {
             int y[3], blocked = 0;
+            double cu = 0.0; /* c_opp(i) . U summed over the crossed faces */
             for (int a = 0; a < 3; ++a) {
                 int v = x0[a] + CV[i][a];
-                if (q.bc[a] && (v < 0 || v >= q.n[a])) blocked = 1;
+                if (q.bc[a] && (v < 0 || v >= q.n[a])) {
+                    blocked = 1;
+                    const double *U = q.uwall[2 * a + (v < 0 ? 0 : 1)];
+                    for (int b = 0; b < 3; ++b) cu += CV[OPP[i]][b] * U[b];
+                }
                 y[a] = wrap(v, q.n[a]);
             }
-            for (int k = 0; k < 2; ++k) {
-                double val = fpost[(size_t)(k * Q + i) * N + s];
-                if (blocked)
-                    f[(size_t)(k * Q + OPP[i]) * N + s] = val;
-                else
-                    f[(size_t)(k * Q + i) * N + sidx(&q, y[0], y[1], y[2])] = val;
+            if (blocked) {
+                double fr = fpost[(size_t)i * N + s], fb = fpost[(size_t)(Q + i) * N + s];
+                double add = 2.0 * W[OPP[i]] * cu / (1.0 / 3.0); /* rho_w = 1 */
+                f[(size_t)OPP[i] * N + s] = fr + add * xr;
+                f[(size_t)(Q + OPP[i]) * N + s] = fb + add * (1.0 - xr);
+            } else {
+                for (int k = 0; k < 2; ++k)
+                    f[(size_t)(k * Q + i) * N + sidx(&q, y[0], y[1], y[2])] = fpost[(size_t)(k * Q + i) * N + s];
             }
         }
     }

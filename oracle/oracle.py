@@ -100,6 +100,7 @@ class Params:
     body_force: tuple = (0.0, 0.0, 0.0)
     eps_g: float = 1e-12
     g_iface: float = 0.05
+    wall_velocity: tuple = ((0.0, 0.0, 0.0),) * 6   # faces -x, +x, -y, +y, -z, +z
 
     @property
     def shape(self):
@@ -108,7 +109,9 @@ class Params:
     def vec(self) -> np.ndarray:
         return np.array([self.nx, self.ny, self.nz, *self.bc, self.tau_r, self.tau_b,
                          self.A, self.beta, self.nc_strength, self.nc_range, self.nc_hmin,
-                         *self.body_force, self.eps_g, self.g_iface], dtype=np.float64)
+                         *self.body_force, self.eps_g, self.g_iface,
+                         *np.asarray(self.wall_velocity, dtype=np.float64).reshape(18)],
+                        dtype=np.float64)
 
 
 def tables():

@@ -52,6 +52,9 @@ int validate_params(const lb_params* p, std::string& why) {
     if (!(p->nc_hmin > 0.0) && p->nc_range > 0 && p->nc_strength > 0) return why = "nc_hmin must be > 0", LB_EINVAL;
     for (int a = 0; a < 3; ++a)
         if (!std::isfinite(p->body_force[a])) return why = "body_force must be finite", LB_EINVAL;
+    for (int f = 0; f < 6; ++f)
+        for (int a = 0; a < 3; ++a)
+            if (!std::isfinite(p->wall_velocity[f][a])) return why = "wall_velocity must be finite", LB_EINVAL;
     if (p->scale_log2 < 0 || p->scale_log2 > 24) return why = "scale_log2 outside 0..24", LB_EINVAL;
     if (!std::isfinite(p->eps_g) || !std::isfinite(p->g_iface)) return why = "eps_g, g_iface must be finite", LB_EINVAL;
     return LB_OK;
@@ -88,6 +91,12 @@ Geom make_geom(const lb_params& p) {
     g.wz = p.bc[2];
     g.nxy = p.nx * p.ny;
     g.N = p.nx * p.ny * p.nz;
+    g.moving = 0;
+    for (int f = 0; f < 6; ++f)
+        for (int a = 0; a < 3; ++a) {
+            g.uw[f][a] = p.wall_velocity[f][a];
+            if (p.wall_velocity[f][a] != 0.0 && p.bc[f / 2]) g.moving = 1;
+        }
     return g;
 }
 
@@ -117,6 +126,7 @@ struct lb_t {
     int cur;           // buffer holding the current state
     int64_t steps;
     bool initialised;
+    bool fresh;        // the state was set (init/import), no collision since: no wall terms
     int kernel;        // LB_KERNEL_TWOPASS or LB_KERNEL_FUSED
     Coeffs<double> cd;
     Coeffs<float> cf;
@@ -128,6 +138,7 @@ lbm::LatticeView view_of(lb_t* h) {
     lbm::LatticeView v;
     v.p = &h->p;
     v.g = h->g;
+    if (h->fresh) v.g.moving = 0;
     v.stream = h->stream;
     v.cur = h->buf[h->cur];
     v.nxt = h->buf[h->cur ^ 1];
@@ -256,6 +267,7 @@ int lb_init_fields(lb_t* h, const void* rho_r, const void* rho_b, const void* u,
     }
     if (rc) return rc;
     h->initialised = true;
+    h->fresh = true;
     h->steps = 0;
     return LB_OK;
 }
@@ -294,6 +306,7 @@ int lb_init_droplets(lb_t* h, const double* centres, const double* radii, int32_
     (void)hipFree(tmp);
     if (rc) return rc;
     h->initialised = true;
+    h->fresh = true;
     h->steps = 0;
     return LB_OK;
 }
@@ -314,6 +327,7 @@ int lb_step(lb_t* h, int32_t n) {
         }
         h->cur ^= 1;
         h->steps++;
+        h->fresh = false;
     }
     return LB_OK;
 }
@@ -339,6 +353,7 @@ int lb_step_timed(lb_t* h, int32_t n, double kernel_ms[3]) {
         }
         h->cur ^= 1;
         h->steps++;
+        h->fresh = false;
     }
     if (!rc) rc = check_hip(hipStreamSynchronize(h->stream), "sync");
     double a = 0, b = 0, c = 0;
@@ -455,6 +470,7 @@ int lb_set_state(lb_t* h, const void* f, int32_t dtype, int32_t on_device) {
     }
     if (rc) return rc;
     h->initialised = true;
+    h->fresh = true;
     return LB_OK;
 }
 
@@ -485,6 +501,7 @@ int lb_load_raw(lb_t* h, const void* src, int32_t on_device) {
         h->pending = nullptr;
     }
     h->initialised = true;
+    h->fresh = false;
     return LB_OK;
 }
 

@@ -1,6 +1,7 @@
-// lb_batch.hip -- many independent lattices (jobs) advanced together: one
-// persistent launch per step walks a work list of (job, tile) items, with the
-// fused single-pass tile body; steps are replayed from a captured HIP graph.
+// lb_batch.hip -- many independent lattices (jobs) advanced together: each
+// step is one persistent phase-pass launch and one persistent collide-pass
+// launch, each walking a work list of (job, tile) items with the same tile
+// bodies as a single lattice; steps are replayed from a captured HIP graph.
 //
 // Each job has a window [first, last) of global steps.  A device counter holds
 // the global step; the step kernel reads it, skips jobs outside their window
@@ -38,10 +39,12 @@ struct BatchJob {
     Coeffs<R> c;
     FusedShape fs;
     void* buf[2];
+    void* phi;              // phase field of the job
     long long first, last;  // global-step window
     int active;
     int tiles;              // tiles_x * tiles_y
-    int pad[2];
+    int fresh;              // the step at `first` reads an initial (not collided) state
+    int pad;
 };
 
 struct WorkItem {
@@ -79,35 +82,74 @@ __device__ __forceinline__ SplitPop<__hip_bfloat16> storage_view<SplitPop<__hip_
     return split_storage_view<__hip_bfloat16>(buf, N, scale);
 }
 
-// One step of every active job.  The grid is fixed (persistent); workgroup b
-// takes items b', b' + G, ... where b' spreads contiguous item runs over the
-// 8 XCDs so neighbouring tiles of a job share an L2.
-template <typename R, typename S>
-__global__ __launch_bounds__(kBatchThreads, Occupancy<S>::waves) void batch_step_kernel(const BatchJob<R>* __restrict__ jobs,
-                                                                   const WorkItem* __restrict__ items,
-                                                                   const int* __restrict__ n_items,
-                                                                   const long long* __restrict__ gstep, float scale) {
-    extern __shared__ unsigned char lds_raw[];
-    const int n = *n_items;
-    const long long gs = *gstep;
+// The two passes of one step of every active job.  The grid is fixed
+// (persistent); workgroup b takes items b', b' + G, ... where b' spreads
+// contiguous item runs over the 8 XCDs so neighbouring tiles of a job share
+// an L2.
+__device__ __forceinline__ int persistent_start() {
     const int G = gridDim.x;
     int b = blockIdx.x;
     if ((G & 7) == 0) b = (b & 7) * (G >> 3) + (b >> 3);
-    for (int w = b; w < n; w += G) {
+    return b;
+}
+
+template <typename R>
+__device__ __forceinline__ void item_tile(const BatchJob<R>& J, const WorkItem& it, int& x0, int& y0, int& za,
+                                          int& zb) {
+    const int tile = it.block % J.tiles;
+    const int chunk = it.block / J.tiles;
+    x0 = (tile % J.fs.tiles_x) * kBatchTX;
+    y0 = (tile / J.fs.tiles_x) * J.fs.TY;
+    za = chunk * J.fs.TZ;
+    zb = min(za + J.fs.TZ, J.g.nz);
+}
+
+template <typename R, typename S>
+__global__ __launch_bounds__(kBatchThreads, Occupancy<S>::waves) void batch_phase_kernel(
+    const BatchJob<R>* __restrict__ jobs, const WorkItem* __restrict__ items, const int* __restrict__ n_items,
+    const long long* __restrict__ gstep, float scale) {
+    extern __shared__ unsigned char lds_raw[];
+    const int n = *n_items;
+    const long long gs = *gstep;
+    for (int w = persistent_start(); w < n; w += gridDim.x) {
+        const WorkItem it = items[w];
+        const BatchJob<R>& J = jobs[it.slot];
+        if (!J.active || gs < J.first || gs >= J.last) continue;  // uniform over the workgroup
+        const int par = (int)((gs - J.first) & 1);
+        const S src = storage_view<S>(J.buf[par], (size_t)J.g.N, scale);
+        int x0, y0, za, zb;
+        item_tile(J, it, x0, y0, za, zb);
+        RecRing<kBatchTX> rr{reinterpret_cast<f4*>(lds_raw), J.fs.TY + 2};
+        Geom g = J.g;
+        if (gs == J.first && J.fresh) g.moving = 0;  // the initial state was not collided
+        phase_tile<R, S, kBatchTX>(g, src, (R*)J.phi, rr, J.fs.TY, x0, y0, za, zb);
+    }
+}
+
+template <typename R, typename S>
+__global__ __launch_bounds__(kBatchThreads, Occupancy<S>::waves) void batch_collide_kernel(
+    const BatchJob<R>* __restrict__ jobs, const WorkItem* __restrict__ items, const int* __restrict__ n_items,
+    const long long* __restrict__ gstep, float scale) {
+    extern __shared__ unsigned char lds_raw[];
+    const int n = *n_items;
+    const long long gs = *gstep;
+    for (int w = persistent_start(); w < n; w += gridDim.x) {
         const WorkItem it = items[w];
         const BatchJob<R>& J = jobs[it.slot];
         if (!J.active || gs < J.first || gs >= J.last) continue;  // uniform over the workgroup
         const int par = (int)((gs - J.first) & 1);
         const S src = storage_view<S>(J.buf[par], (size_t)J.g.N, scale);
         const S dst = storage_view<S>(J.buf[par ^ 1], (size_t)J.g.N, scale);
-        const int tile = it.block % J.tiles;
-        const int chunk = it.block / J.tiles;
-        const int x0 = (tile % J.fs.tiles_x) * kBatchTX;
-        const int y0 = (tile / J.fs.tiles_x) * J.fs.TY;
-        const int za = chunk * J.fs.TZ;
-        const int zb = min(za + J.fs.TZ, J.g.nz);
+        int x0, y0, za, zb;
+        item_tile(J, it, x0, y0, za, zb);
         PhiRing<R, kBatchTX, kBatchH> ring{reinterpret_cast<R*>(lds_raw), J.fs.TY + 2 * kBatchH};
-        fused_tile<R, S, S, kBatchTX, kBatchH>(J.g, src, dst, J.c, ring, J.fs.TY, x0, y0, za, zb);
+        RecRing<kBatchTX> rr{reinterpret_cast<f4*>(lds_raw + ((phi_ring_bytes<R, kBatchTX, kBatchH>(J.fs.TY) + 15) &
+                                                               ~size_t(15))),
+                             J.fs.TY + 2};
+        Geom g = J.g;
+        if (gs == J.first && J.fresh) g.moving = 0;  // the initial state was not collided
+        fused_tile<R, S, S, kBatchTX, kBatchH>(g, src, dst, J.c, ring, J.fs.TY, x0, y0, za, zb,
+                                               (const R*)J.phi, rr);
     }
 }
 
@@ -115,11 +157,17 @@ __global__ void batch_tick_kernel(long long* gstep) {
     if (blockIdx.x == 0 && threadIdx.x == 0) gstep[0] = gstep[0] + 1;
 }
 
-int batch_rows(int storage) { return storage == LB_STORE_F64 ? 8 : 16; }
+int batch_rows(int storage) { return storage == LB_STORE_F64 ? 8 : 4; }
 
-size_t batch_lds(int storage) {
-    const size_t rs = storage == LB_STORE_F64 ? 8 : 4;
-    return (size_t)(2 * kBatchH + 1) * (batch_rows(storage) + 2 * kBatchH) * (kBatchTX + 2 * kBatchH) * rs;
+size_t batch_phase_lds(int storage) {
+    return storage >= LB_STORE_F16 ? rec_ring_bytes<kBatchTX>(batch_rows(storage)) : 0;
+}
+
+size_t batch_collide_lds(int storage) {
+    const int TY = batch_rows(storage);
+    const size_t phi = storage == LB_STORE_F64 ? phi_ring_bytes<double, kBatchTX, kBatchH>(TY)
+                                               : phi_ring_bytes<float, kBatchTX, kBatchH>(TY);
+    return ((phi + 15) & ~size_t(15)) + batch_phase_lds(storage);
 }
 
 }  // namespace lbm
@@ -188,6 +236,7 @@ struct HostJob {
     lb_params p;
     size_t off = 0, bytes = 0;
     long long first = 0, last = 0;
+    bool fresh = false;
     Coeffs<double> cd;
     Coeffs<float> cf;
     FusedShape fs;
@@ -219,7 +268,13 @@ struct lb_batch_t {
 
 namespace {
 
-size_t job_bytes(int storage, size_t N) { return 2 * lbm::pop_bytes(storage, N); }
+// Two population buffers and the phase field.
+size_t job_bytes(int storage, size_t N) {
+    const size_t half = (lbm::pop_bytes(storage, N) + 255) & ~size_t(255);
+    return 2 * half + N * (storage == LB_STORE_F64 ? 8 : 4);
+}
+
+size_t job_half(int storage, size_t N) { return (lbm::pop_bytes(storage, N) + 255) & ~size_t(255); }
 
 float batch_scale(const lb_batch_t* b, const lb_params& p) {
     return b->storage == LB_STORE_F16 ? std::ldexp(1.0f, p.scale_log2 ? p.scale_log2 : 16) : 1.0f;
@@ -230,7 +285,7 @@ FusedShape job_shape(int storage, const lb_params& p) {
     fs.TY = batch_rows(storage);
     fs.tiles_x = (p.nx + kBatchTX - 1) / kBatchTX;
     fs.tiles_y = (p.ny + fs.TY - 1) / fs.TY;
-    fs.TZ = std::min(p.nz, 32);
+    fs.TZ = std::min(p.nz, 16);
     fs.chunks = (p.nz + fs.TZ - 1) / fs.TZ;
     fs.nblocks = fs.tiles_x * fs.tiles_y * fs.chunks;
     return fs;
@@ -245,13 +300,15 @@ void fill_desc(const lb_batch_t* b, const HostJob& h, BatchJob<R>& d) {
     else
         d.c = h.cf;
     d.fs = h.fs;
-    const size_t half = h.bytes / 2;
+    const size_t half = job_half(b->storage, (size_t)h.p.nx * h.p.ny * h.p.nz);
     d.buf[0] = b->arena_base + h.off;
     d.buf[1] = b->arena_base + h.off + half;
+    d.phi = b->arena_base + h.off + 2 * half;
     d.first = h.first;
     d.last = h.last;
     d.active = h.used ? 1 : 0;
     d.tiles = h.fs.tiles_x * h.fs.tiles_y;
+    d.fresh = h.fresh ? 1 : 0;
 }
 
 size_t desc_size(int storage) { return storage == LB_STORE_F64 ? sizeof(BatchJob<double>) : sizeof(BatchJob<float>); }
@@ -301,10 +358,14 @@ int upload_items(lb_batch_t* b) {
 template <typename R, typename S>
 int launch_batch_step(lb_batch_t* b) {
     const float sc = b->storage == LB_STORE_F16 ? std::ldexp(1.0f, 16) : 1.0f;
-    hipLaunchKernelGGL((batch_step_kernel<R, S>), dim3(b->grid), dim3(kBatchThreads), batch_lds(b->storage), b->stream,
-                       (const BatchJob<R>*)b->d_jobs, b->d_items, b->d_nitems, b->d_gstep, sc);
+    hipLaunchKernelGGL((batch_phase_kernel<R, S>), dim3(b->grid), dim3(kBatchThreads), batch_phase_lds(b->storage),
+                       b->stream, (const BatchJob<R>*)b->d_jobs, b->d_items, b->d_nitems, b->d_gstep, sc);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return bfail(LB_EDEVICE, std::string("batch_step_kernel: ") + hipGetErrorString(e));
+    if (e != hipSuccess) return bfail(LB_EDEVICE, std::string("batch_phase_kernel: ") + hipGetErrorString(e));
+    hipLaunchKernelGGL((batch_collide_kernel<R, S>), dim3(b->grid), dim3(kBatchThreads), batch_collide_lds(b->storage),
+                       b->stream, (const BatchJob<R>*)b->d_jobs, b->d_items, b->d_nitems, b->d_gstep, sc);
+    e = hipGetLastError();
+    if (e != hipSuccess) return bfail(LB_EDEVICE, std::string("batch_collide_kernel: ") + hipGetErrorString(e));
     hipLaunchKernelGGL(batch_tick_kernel, dim3(1), dim3(64), 0, b->stream, b->d_gstep);
     e = hipGetLastError();
     if (e != hipSuccess) return bfail(LB_EDEVICE, std::string("batch_tick_kernel: ") + hipGetErrorString(e));
@@ -369,12 +430,22 @@ LatticeView job_view(lb_batch_t* b, int slot, void* cur, void* nxt, void* pendin
     return v;
 }
 
+// View of a job's current state for export and moments.
+LatticeView current_view(lb_batch_t* b, int slot);
+
 // Buffer holding a job's current state.
 void* job_current(lb_batch_t* b, int slot) {
     HostJob& h = b->jobs[slot];
     const long long done = std::min(b->gstep, h.last) - h.first;
-    const size_t half = h.bytes / 2;
+    const size_t half = job_half(b->storage, (size_t)h.p.nx * h.p.ny * h.p.nz);
     return b->arena_base + h.off + ((done & 1) ? half : 0);
+}
+
+LatticeView current_view(lb_batch_t* b, int slot) {
+    HostJob& h = b->jobs[slot];
+    LatticeView v = job_view(b, slot, job_current(b, slot), nullptr, nullptr);
+    if (h.fresh && std::min(b->gstep, h.last) == h.first) v.g.moving = 0;  // not collided yet
+    return v;
 }
 
 }  // namespace
@@ -482,7 +553,7 @@ static int batch_admit(lb_batch_t* b, const lb_params* params, int64_t steps, in
     h.cf = make_coeffs<float>(h.p);
     h.fs = job_shape(b->storage, h.p);
     char* b0 = b->arena_base + off;
-    char* b1 = b0 + bytes / 2;
+    char* b1 = b0 + job_half(b->storage, N);
     const bool split = b->storage >= LB_STORE_F16;
     int rc = LB_OK;
     long long done = 0;
@@ -490,6 +561,7 @@ static int batch_admit(lb_batch_t* b, const lb_params* params, int64_t steps, in
         rc = ensure_staging(b, lbm::pop_bytes(LB_STORE_F32, N) + 5 * N * sizeof(double));
         if (!rc) {
             LatticeView v = job_view(b, s, b0, b1, b->staging);
+            v.g.moving = 0;  // the first step reads the initial, not collided, state
             rc = init(b, v, ctx);
             if (!rc && steps > 0) {
                 rc = launch_step(v, LB_KERNEL_FUSED, nullptr);
@@ -510,6 +582,7 @@ static int batch_admit(lb_batch_t* b, const lb_params* params, int64_t steps, in
         return rc;
     }
     h.used = true;
+    h.fresh = (done == 0);
     h.first = b->gstep - done;
     h.last = h.first + steps;
     rc = upload_desc(b, s);
@@ -647,7 +720,7 @@ int lb_batch_moments(lb_batch_t* b, int32_t slot, void* rho_r, void* rho_b, void
     HostJob& h = b->jobs[slot];
     const size_t N = (size_t)h.p.nx * h.p.ny * h.p.nz;
     const size_t es = dtype == LB_DTYPE_F64 ? 8 : 4;
-    LatticeView v = job_view(b, slot, job_current(b, slot), nullptr, nullptr);
+    LatticeView v = current_view(b, slot);
     int rc = LB_OK;
     if (rho_r || rho_b || mom) {
         if (!on_device) rc = ensure_staging(b, 5 * N * es + 64);
@@ -694,7 +767,7 @@ int lb_batch_get_state(lb_batch_t* b, int32_t slot, void* f, int32_t dtype, int3
         if (rc) return rc;
         out = b->staging;
     }
-    LatticeView v = job_view(b, slot, job_current(b, slot), nullptr, nullptr);
+    LatticeView v = current_view(b, slot);
     rc = launch_export(v, out, dtype);
     if (!rc && !on_device) rc = bcheck(hipMemcpyAsync(f, out, bytes, hipMemcpyDeviceToHost, b->stream), "D2H state");
     if (!rc) rc = bcheck(hipStreamSynchronize(b->stream), "sync");

@@ -5,6 +5,7 @@
 #include <string>
 
 #include "lb.h"
+#include "lb_fused.hpp"
 #include "lb_kernels.hpp"
 
 namespace lbm {
@@ -32,6 +33,15 @@ template <typename R>
 Coeffs<R> make_coeffs(const lb_params& p);
 Geom make_geom(const lb_params& p);
 size_t pop_bytes(int storage, size_t N);
+
+// Tile kernels: 64-wide tiles of TY rows marching z-chunks of TZ planes.
+constexpr int kTX = 64;
+enum TileKind { TILE_COLLIDE = 0, TILE_FUSED = 1, TILE_PHASE = 2 };
+int env_int(const char* name, int dflt);
+int tile_halo(const lb_params& p);
+size_t tile_lds(const lb_params& p, int kind, int TY);
+int tile_rows(const lb_params& p, int kind);
+FusedShape tile_shape(const lb_params& p, int kind, int target_blocks = 1024);
 
 int choose_kernel(const lb_params& p);
 // Events recorded around the passes of one step (null = no timing):

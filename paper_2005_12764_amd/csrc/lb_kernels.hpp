@@ -19,6 +19,8 @@ struct Geom {
     int wx, wy, wz;  // 1 = halfway bounce-back walls on that axis
     int nxy;
     int N;
+    int moving;      // some wall face moves (its reflections get a momentum term)
+    double uw[6][3]; // wall face velocities, faces -x, +x, -y, +y, -z, +z
 };
 
 __device__ __forceinline__ void site_xyz(const Geom& g, int s, int& x, int& y, int& z) {
@@ -66,6 +68,24 @@ __device__ __forceinline__ int pull_source(const Geom& g, int i, int x, int y, i
     return bb ? s : site_of(g, xs, ys, zs);
 }
 
+// Moving-wall term of direction i arriving at (x,y,z) by reflection:
+// 2 w_i (c_i . U)/c_s^2 summed over the wall faces the upstream site x - c_i
+// lies beyond (reference density 1).
+__device__ __forceinline__ double wall_term(const Geom& g, int i, int x, int y, int z) {
+    using L = Lattice;
+    double cu = 0.0;
+    const int v[3] = {x - L::cx[i], y - L::cy[i], z - L::cz[i]};
+    const int n[3] = {g.nx, g.ny, g.nz};
+    const int w[3] = {g.wx, g.wy, g.wz};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (!w[a] || (v[a] >= 0 && v[a] < n[a])) continue;
+        const double* U = g.uw[2 * a + (v[a] < 0 ? 0 : 1)];
+        cu += L::cx[i] * U[0] + L::cy[i] * U[1] + L::cz[i] * U[2];
+    }
+    return 6.0 * weight<double>(i) * cu;
+}
+
 // ---------------------------------------------------------------------------
 // Storage policies.  pull() gathers the post-streaming populations of a site
 // from the post-collision buffer of the previous step; store() writes the
@@ -88,6 +108,32 @@ struct RawPop {
             fr[i] = R(f[(size_t)d * N + src]);
             fb[i] = R(f[(size_t)(Q + d) * N + src]);
         }
+        if (g.moving) add_wall_terms<R>(g, s, x, y, z, fr, fb);
+    }
+
+    // Moving-wall terms of the reflected directions, shared by the site's own
+    // post-collision colour fraction.
+    template <typename R>
+    __device__ void add_wall_terms(const Geom& g, int s, int x, int y, int z, R (&fr)[Q], R (&fb)[Q]) const {
+        R a = R(0), b = R(0);
+        bool have = false;
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            int d;
+            (void)pull_source(g, i, x, y, z, s, d);
+            if (d == i) continue;
+            if (!have) {
+                for (int j = 0; j < Q; ++j) {
+                    a += R(f[(size_t)j * N + s]);
+                    b += R(f[(size_t)(Q + j) * N + s]);
+                }
+                have = true;
+            }
+            const R add = R(wall_term(g, i, x, y, z));
+            const R xr = a / (a + b);
+            fr[i] += add * xr;
+            fb[i] += add * (R(1) - xr);
+        }
     }
     template <typename R>
     __device__ __forceinline__ void store(int s, const R (&fr)[Q], const R (&fb)[Q],
@@ -99,6 +145,7 @@ struct RawPop {
         }
     }
     static constexpr bool needs_totals = false;
+    static constexpr bool ring = false;
 };
 
 template <typename H>
@@ -116,6 +163,22 @@ struct Half<__hip_bfloat16> {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
+// The 16-bit pull decodes directions in groups and pins each group's decoded
+// values in registers (an empty asm with the values as operands, no code)
+// before the next group: otherwise the compiler keeps all 19 source records
+// (8 floats each) live at once, ~200 VGPRs and two waves per SIMD; with
+// groups of 5 the step kernels fit in ~116 VGPRs.
+#ifndef LB_DECODE_GROUP
+#define LB_DECODE_GROUP 5
+#endif
+constexpr int kDecodeGroup = LB_DECODE_GROUP;
+
+template <typename R>
+__device__ __forceinline__ void pin_group(int last, R (&fr)[Q], R (&fb)[Q]) {
+#pragma unroll
+    for (int j = last - (last % kDecodeGroup); j <= last; ++j) asm volatile("" : "+v"(fr[j]), "+v"(fb[j]));
+}
+
 // 16-bit moment-split storage.  Per site, 8 FP32 values rec[N][8] (two
 // 16-byte vectors per site): density,
 // velocity (3), red fraction, recolouring vector (3) of the post-collision
@@ -130,32 +193,81 @@ struct SplitPop {
     size_t N;
     float scale, inv_scale;
 
+    // Decode direction i (read as d = i, or opp(i) after a bounce-back) from
+    // the source's record (ra, rb) and its 16-bit deviation.
+    template <typename R>
+    __device__ __forceinline__ void decode(int i, int d, const f4& ra, const f4& rb, H dv16, R& fr_i,
+                                           R& fb_i) const {
+        using L = Lattice;
+        const float rho = ra.x, ux = ra.y, uy = ra.z, uz = ra.w;
+        const float xr = rb.x, vx = rb.y, vy = rb.z, vz = rb.w;
+        const float dv = Half<H>::to_f(dv16) * inv_scale;
+        // direction d is i, or its opposite after a bounce-back (same shell)
+        const float sg = (d == i) ? 1.0f : -1.0f;
+        const float cdx = sg * float(L::cx[i]), cdy = sg * float(L::cy[i]), cdz = sg * float(L::cz[i]);
+        const float cu = cdx * ux + cdy * uy + cdz * uz;
+        const float uu = ux * ux + uy * uy + uz * uz;
+        const float w = weight<float>(i);
+        const float ic = inv_clen<float>(i);
+        const float fs = rho * (w * (1.0f + 3.0f * cu + 4.5f * cu * cu - 1.5f * uu)) + dv;
+        const float r = xr * fs + w * (cdx * vx + cdy * vy + cdz * vz) * ic;
+        fr_i = R(r);
+        fb_i = R(fs - r);
+    }
+
     template <typename R>
     __device__ __forceinline__ void pull(const Geom& g, int s, int x, int y, int z, R (&fr)[Q],
                                          R (&fb)[Q]) const {
-        using L = Lattice;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             int d;
             const int src = pull_source(g, i, x, y, z, s, d);
             const f4 ra = *reinterpret_cast<const f4*>(rec + 8 * (size_t)src);
             const f4 rb = *reinterpret_cast<const f4*>(rec + 8 * (size_t)src + 4);
-            const float rho = ra.x, ux = ra.y, uy = ra.z, uz = ra.w;
-            const float xr = rb.x, vx = rb.y, vy = rb.z, vz = rb.w;
-            const float dv = Half<H>::to_f(dev[(size_t)d * N + src]) * inv_scale;
-            // direction d is i, or its opposite after a bounce-back (same shell)
-            const float sg = (d == i) ? 1.0f : -1.0f;
-            const float cdx = sg * float(L::cx[i]), cdy = sg * float(L::cy[i]), cdz = sg * float(L::cz[i]);
-            const float cu = cdx * ux + cdy * uy + cdz * uz;
-            const float uu = ux * ux + uy * uy + uz * uz;
-            const float w = weight<float>(i);
-            const float ic = inv_clen<float>(i);
-            const float fs = rho * (w * (1.0f + 3.0f * cu + 4.5f * cu * cu - 1.5f * uu)) + dv;
-            const float r = xr * fs + w * (cdx * vx + cdy * vy + cdz * vz) * ic;
-            fr[i] = R(r);
-            fb[i] = R(fs - r);
+            decode<R>(i, d, ra, rb, dev[(size_t)d * N + src], fr[i], fb[i]);
+            if (i % kDecodeGroup == kDecodeGroup - 1 || i == Q - 1) pin_group(i, fr, fb);
+        }
+        if (g.moving) add_wall_terms<R>(g, s, x, y, z, rec[8 * (size_t)s + 4], fr, fb);
+    }
+
+    // Moving-wall terms of the reflected directions, shared by the site's own
+    // post-collision red fraction xr (from its record).
+    template <typename R>
+    __device__ void add_wall_terms(const Geom& g, int s, int x, int y, int z, float xr, R (&fr)[Q],
+                                   R (&fb)[Q]) const {
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            int d;
+            (void)pull_source(g, i, x, y, z, s, d);
+            if (d == i) continue;
+            const R add = R(wall_term(g, i, x, y, z));
+            fr[i] += add * R(xr);
+            fb[i] += add * (R(1) - R(xr));
         }
     }
+
+    // As pull(), with the source records taken from an LDS ring that holds
+    // the records of planes z-1, z, z+1 around the tile (one-site halo):
+    // `ring[k]` points at the plane of z - 1 + k, (ly, lx) is the site's
+    // position in the ring plane, LXR its row length.
+    template <typename R>
+    __device__ __forceinline__ void pull_ring(const Geom& g, int s, int x, int y, int z, R (&fr)[Q],
+                                              R (&fb)[Q], const f4* const (&ring)[3], int ly, int lx,
+                                              int LXR) const {
+        using L = Lattice;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            int d;
+            const int src = pull_source(g, i, x, y, z, s, d);
+            const bool bb = (d != i);
+            const f4* pl = bb ? ring[1] : ring[1 - L::cz[i]];
+            const int pos = bb ? (ly * LXR + lx) : ((ly - L::cy[i]) * LXR + lx - L::cx[i]);
+            decode<R>(i, d, pl[2 * pos], pl[2 * pos + 1], dev[(size_t)d * N + src], fr[i], fb[i]);
+            if (i % kDecodeGroup == kDecodeGroup - 1 || i == Q - 1) pin_group(i, fr, fb);
+        }
+        if (g.moving) add_wall_terms<R>(g, s, x, y, z, ring[1][2 * (ly * LXR + lx) + 1].x, fr, fb);
+    }
+
     template <typename R>
     __device__ __forceinline__ void store(int s, const R (&fr)[Q], const R (&fb)[Q],
                                           const SiteTotals<R>& t) const {
@@ -172,6 +284,7 @@ struct SplitPop {
         }
     }
     static constexpr bool needs_totals = true;
+    static constexpr bool ring = true;
 };
 
 // Minimum waves per SIMD the step kernels ask the compiler for, per storage.

@@ -15,6 +15,9 @@ namespace lbm {
 namespace {
 
 constexpr int kBlock = 256;
+int max_lds_bytes();
+size_t real_size(const lb_params& p);
+bool split_storage(const lb_params& p);
 
 int launch_status(const char* what) {
     hipError_t e = hipGetLastError();
@@ -55,8 +58,6 @@ int with_state(const LatticeView& v, Fn&& fn) {
     return set_error(LB_EINVAL, "unknown storage");
 }
 
-constexpr int kTX = 64;
-
 int max_lds_bytes() {
     static int cached = -1;
     if (cached < 0) {
@@ -69,56 +70,17 @@ int max_lds_bytes() {
     return cached;
 }
 
-int env_int(const char* name, int dflt) {
-    const char* e = std::getenv(name);
-    return (e && *e) ? std::atoi(e) : dflt;
-}
-
-// Halo of the fused kernel: the colour gradient needs one site, the
-// near-contact probe K more.
-int fused_halo(const lb_params& p) { return 1 + ((p.nc_strength > 0.0) ? p.nc_range : 0); }
-
 size_t real_size(const lb_params& p) { return p.storage == LB_STORE_F64 ? 8 : 4; }
 
-size_t fused_lds(const lb_params& p, int TY) {
-    const int H = fused_halo(p);
-    return (size_t)(2 * H + 1) * (TY + 2 * H) * (kTX + 2 * H) * real_size(p);
-}
-
-// Tile rows: the largest that keeps the phi ring within the LDS budget.
-int fused_rows(const lb_params& p) {
-    const int want = env_int("LB_FUSED_TY", 0);
-    if (want > 0) return fused_lds(p, want) <= (size_t)max_lds_bytes() ? want : 0;
-    for (int ty : {16, 8, 4, 2})
-        if (fused_lds(p, ty) <= (size_t)max_lds_bytes()) return ty;
-    return 0;
-}
-
-FusedShape fused_shape(const lb_params& p) {
-    FusedShape fs;
-    fs.TY = fused_rows(p);
-    fs.tiles_x = (p.nx + kTX - 1) / kTX;
-    fs.tiles_y = (p.ny + fs.TY - 1) / fs.TY;
-    const int tiles = fs.tiles_x * fs.tiles_y;
-    int tz = env_int("LB_FUSED_TZ", 0);
-    if (tz <= 0) {
-        // aim for >= 1024 workgroups, but keep chunks >= 4 * halo planes deep
-        const int H = fused_halo(p);
-        const int want_chunks = std::max(1, 1024 / std::max(1, tiles));
-        tz = std::max(4 * H, (p.nz + want_chunks - 1) / want_chunks);
-    }
-    fs.TZ = std::min(tz, p.nz);
-    fs.chunks = (p.nz + fs.TZ - 1) / fs.TZ;
-    fs.nblocks = tiles * fs.chunks;
-    return fs;
-}
+bool split_storage(const lb_params& p) { return p.storage >= LB_STORE_F16; }
 
 // z-marching tile kernel: phi_in == nullptr computes phi itself (single
 // pass), otherwise reads the phase pass's phi (collide pass of two-pass).
 template <typename R, typename Src, typename Dst, int H>
 int zmarch_h(const LatticeView& v, const Src& src, const Dst& dst, const Coeffs<R>& c, const R* phi_in) {
-    const FusedShape fs = fused_shape(*v.p);
-    const size_t lds = (size_t)(2 * H + 1) * (fs.TY + 2 * H) * (kTX + 2 * H) * sizeof(R);
+    const int kind = phi_in ? TILE_COLLIDE : TILE_FUSED;
+    const FusedShape fs = tile_shape(*v.p, kind);
+    const size_t lds = tile_lds(*v.p, kind, fs.TY);
     hipLaunchKernelGGL((fused_kernel<R, Src, Dst, kTX, H>), dim3(fs.nblocks), dim3(kBlock), lds, v.stream, v.g, src,
                        dst, c, fs, phi_in);
     return launch_status(phi_in ? "collide pass" : "fused_kernel");
@@ -126,7 +88,7 @@ int zmarch_h(const LatticeView& v, const Src& src, const Dst& dst, const Coeffs<
 
 template <typename R, typename Src, typename Dst>
 int zmarch(const LatticeView& v, const Src& src, const Dst& dst, const Coeffs<R>& c, const R* phi_in) {
-    switch (fused_halo(*v.p)) {
+    switch (tile_halo(*v.p)) {
         case 1: return zmarch_h<R, Src, Dst, 1>(v, src, dst, c, phi_in);
         case 2: return zmarch_h<R, Src, Dst, 2>(v, src, dst, c, phi_in);
         case 3: return zmarch_h<R, Src, Dst, 3>(v, src, dst, c, phi_in);
@@ -147,22 +109,36 @@ int fused(const LatticeView& v, const Src& src, const Dst& dst, const Coeffs<R>&
     return rc;
 }
 
+// Phase pass: raw storage pulls site by site; 16-bit moment-split storage
+// runs z-marching tiles with the source records staged in LDS.
+template <typename R, typename Src>
+int phase_pass(const LatticeView& v, const Src& src) {
+    if constexpr (Src::ring) {
+        if (tile_rows(*v.p, TILE_PHASE) > 0) {
+            const FusedShape fs = tile_shape(*v.p, TILE_PHASE);
+            hipLaunchKernelGGL((phase_tile_kernel<R, Src, kTX>), dim3(fs.nblocks), dim3(kBlock),
+                               tile_lds(*v.p, TILE_PHASE, fs.TY), v.stream, v.g, src, (R*)v.phi, fs);
+            return launch_status("phase_tile_kernel");
+        }
+    }
+    hipLaunchKernelGGL((phase_kernel<R, Src>), dim3(grid_for(v.g.N)), dim3(kBlock), 0, v.stream, v.g, src, (R*)v.phi);
+    return launch_status("phase_kernel");
+}
+
 // Two passes: the phase pass writes phi; the collide pass z-marches tiles
 // with phi in an LDS ring (or, when the ring does not fit, reads phi from
 // global memory site by site).
 template <typename R, typename Src, typename Dst>
 int two_pass(const LatticeView& v, const Src& src, const Dst& dst, const Coeffs<R>& c, const StepEvents* t) {
-    const unsigned grid = grid_for(v.g.N);
     if (t) (void)hipEventRecord(t->ev[0], v.stream);
-    hipLaunchKernelGGL((phase_kernel<R, Src>), dim3(grid), dim3(kBlock), 0, v.stream, v.g, src, (R*)v.phi);
-    int rc = launch_status("phase_kernel");
+    int rc = phase_pass<R>(v, src);
     if (rc) return rc;
     if (t) (void)hipEventRecord(t->ev[1], v.stream);
-    if (fused_rows(*v.p) > 0 && env_int("LB_TWOPASS_SIMPLE", 0) == 0) {
+    if (tile_rows(*v.p, TILE_COLLIDE) > 0 && env_int("LB_TWOPASS_SIMPLE", 0) == 0) {
         rc = zmarch<R>(v, src, dst, c, (const R*)v.phi);
     } else {
-        hipLaunchKernelGGL((collide_kernel<R, Src, Dst>), dim3(grid), dim3(kBlock), 0, v.stream, v.g, src, dst,
-                           (const R*)v.phi, c);
+        hipLaunchKernelGGL((collide_kernel<R, Src, Dst>), dim3(grid_for(v.g.N)), dim3(kBlock), 0, v.stream, v.g, src,
+                           dst, (const R*)v.phi, c);
         rc = launch_status("collide_kernel");
     }
     if (t) (void)hipEventRecord(t->ev[2], v.stream);
@@ -178,13 +154,66 @@ int step_with(const LatticeView& v, int kernel, const Src& src, const Dst& dst, 
 
 }  // namespace
 
+int env_int(const char* name, int dflt) {
+    const char* e = std::getenv(name);
+    return (e && *e) ? std::atoi(e) : dflt;
+}
+
+int tile_halo(const lb_params& p) { return 1 + ((p.nc_strength > 0.0) ? p.nc_range : 0); }
+
+size_t tile_lds(const lb_params& p, int kind, int TY) {
+    const int H = tile_halo(p);
+    const size_t phi = (size_t)(2 * H + 1) * (TY + 2 * H) * (kTX + 2 * H) * real_size(p);
+    const size_t rec = (size_t)3 * (TY + 2) * (kTX + 2) * 32;
+    const bool split = split_storage(p);
+    switch (kind) {
+        case TILE_PHASE: return rec;
+        case TILE_COLLIDE: return ((phi + 15) & ~size_t(15)) + (split ? rec : 0);
+        default: return phi;
+    }
+}
+
+// Tile rows: preferred per kind and storage (measured on MI355X), else the
+// largest that keeps the LDS rings within the per-workgroup budget.
+int tile_rows(const lb_params& p, int kind) {
+    const char* env = kind == TILE_PHASE ? "LB_PHASE_TY" : "LB_COLLIDE_TY";
+    int want = env_int(env, 0);
+    if (want <= 0) {
+        if (kind == TILE_PHASE) want = 8;
+        else if (split_storage(p)) want = kind == TILE_COLLIDE ? 4 : 8;
+        else want = p.storage == LB_STORE_F64 ? 8 : 4;
+    }
+    for (int ty = want; ty >= 1; ty /= 2)
+        if (tile_lds(p, kind, ty) <= (size_t)max_lds_bytes()) return ty;
+    return 0;
+}
+
+FusedShape tile_shape(const lb_params& p, int kind, int target_blocks) {
+    FusedShape fs;
+    fs.TY = tile_rows(p, kind);
+    fs.tiles_x = (p.nx + kTX - 1) / kTX;
+    fs.tiles_y = (p.ny + fs.TY - 1) / fs.TY;
+    const int tiles = fs.tiles_x * fs.tiles_y;
+    int tz = env_int(kind == TILE_PHASE ? "LB_PHASE_TZ" : "LB_TZ", 0);
+    if (tz <= 0) {
+        // aim for target_blocks workgroups, keeping chunks a few halos deep
+        const int H = kind == TILE_PHASE ? 1 : tile_halo(p);
+        const int want_chunks = std::max(1, target_blocks / std::max(1, tiles));
+        tz = std::max(4 * H, (p.nz + want_chunks - 1) / want_chunks);
+    }
+    fs.TZ = std::min(std::max(tz, 1), p.nz);
+    fs.chunks = (p.nz + fs.TZ - 1) / fs.TZ;
+    fs.nblocks = tiles * fs.chunks;
+    return fs;
+}
+
 int choose_kernel(const lb_params& p) {
-    const bool fits = fused_rows(p) > 0;
+    const bool fits = tile_rows(p, TILE_FUSED) > 0;
     if (p.kernel == LB_KERNEL_TWOPASS) return LB_KERNEL_TWOPASS;
     if (p.kernel == LB_KERNEL_FUSED) return fits ? LB_KERNEL_FUSED : -1;
-    // automatic: the fused kernel once a tile row is mostly interior sites
-    const double N = double(p.nx) * p.ny * p.nz;
-    return (fits && p.nx >= 32 && N >= 32768.0) ? LB_KERNEL_FUSED : LB_KERNEL_TWOPASS;
+    // automatic: two passes (measured faster than the single pass on MI355X:
+    // the single pass's second read of each plane misses the caches)
+    return LB_KERNEL_TWOPASS;
 }
 
 // Source/destination storage pairs a step may combine: same storage, or the

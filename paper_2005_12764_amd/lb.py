@@ -44,6 +44,7 @@ class lb_params(ctypes.Structure):
         ("nc_hmin", ctypes.c_double),
         ("body_force", ctypes.c_double * 3),
         ("eps_g", ctypes.c_double), ("g_iface", ctypes.c_double),
+        ("wall_velocity", (ctypes.c_double * 3) * 6),
     ]
 
 
@@ -64,6 +65,12 @@ def make_params(p: dict) -> lb_params:
     s.nc_hmin = float(p.get("nc_hmin", 2.0))
     s.eps_g = float(p.get("eps_g", 0.0))
     s.g_iface = float(p.get("g_iface", 0.0))
+    uw = p.get("wall_velocity")
+    if uw is not None:
+        uw = np.asarray(uw, dtype=np.float64).reshape(6, 3)
+        for f in range(6):
+            for a in range(3):
+                s.wall_velocity[f][a] = float(uw[f, a])
     return s
 
 

@@ -229,7 +229,8 @@ class Server:
 def make_requests(n_jobs: int, seed: int = 0, rate: float = 40.0, steps: int = 500, workers: int = 16,
                   sides=(32, 48, 64, 96, 128)) -> List[Request]:
     """The design-sweep request stream: Poisson arrivals, per-job parameters
-    and droplet lists (built by the client, in parallel worker processes)."""
+    and droplet lists (built by the client, in parallel worker processes; call
+    it before the calling process initialises the GPU)."""
     jobs = W.job_stream(seed=seed, n_jobs=n_jobs, rate=rate, sides=sides, steps=steps)
     if workers > 1 and n_jobs > 1:
         import multiprocessing as mp
@@ -260,14 +261,15 @@ def main():
     ap.add_argument("--storage", default="f16")
     ap.add_argument("--seed", type=int, default=0)
     args = ap.parse_args()
-    import torch
-    torch.cuda.set_device(0)
     storage = {"f32": W.F32, "f16": W.F16, "bf16": W.BF16}[args.storage]
+    # requests are built by worker processes before this process touches the GPU
     t = time.perf_counter()
     reqs = make_requests(args.jobs, seed=args.seed, rate=args.rate, steps=args.steps)
     for r in reqs:
         r.params = dict(r.params, storage=storage)
     print("[serve] %d requests prepared in %.1fs" % (len(reqs), time.perf_counter() - t), flush=True)
+    import torch
+    torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
     backend = GpuBackend(int(args.budget_gb * 2 ** 30), args.max_jobs, storage, args.chunk, stream)
     with torch.cuda.stream(stream):

@@ -27,7 +27,7 @@ def test_library_exports_every_declared_function():
 
 
 def test_params_struct_matches_header_size():
-    assert ctypes.sizeof(lb.lb_params) == 128
+    assert ctypes.sizeof(lb.lb_params) == 128 + 6 * 3 * 8
 
 
 @pytest.mark.parametrize("bad", [

@@ -46,10 +46,17 @@ def test_job_alone_equals_job_in_mix_and_single_lattice(storage):
         mixed = B.state(sa)
         assert B.job_steps(sa) == steps and B.job_steps(sc) == steps and B.job_steps(sb) == steps + 7
     assert np.array_equal(alone, mixed)
-    with lb.Lattice(dict(a.params, storage=storage, kernel=lb.KERNEL_FUSED)) as L:
-        L.init(a.rho_r, a.rho_b).step(steps)
-        single = L.state()
-    assert np.array_equal(alone, single)
+    # the batch runs the single lattice's two-pass tile code: bitwise equal;
+    # the single-pass kernel evaluates the same formulas in another order of
+    # contraction, so it agrees to rounding
+    for kernel in (lb.KERNEL_TWOPASS, lb.KERNEL_FUSED):
+        with lb.Lattice(dict(a.params, storage=storage, kernel=kernel)) as L:
+            L.init(a.rho_r, a.rho_b).step(steps)
+            single = L.state()
+        if kernel == lb.KERNEL_TWOPASS:
+            assert np.array_equal(alone, single)
+        else:
+            assert state_errors(single, alone)["worst"] < 1e-6
     if storage == W.F32:
         ref = O.step(oracle_params(a.params), O.init(oracle_params(a.params), a.rho_r, a.rho_b), steps)
         assert state_errors(mixed, ref)["worst"] < 1e-5

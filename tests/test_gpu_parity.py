@@ -221,3 +221,39 @@ def test_invalid_use_reports_errors():
         with pytest.raises(lb.LbError) as e:
             L.init(bad, -bad)                          # negative density
         assert e.value.code == lb.LB_EINVAL
+
+
+# ------------------------------------------------------------- sliding walls
+
+SHEAR = ((0, 0, 0), (0, 0, 0), (0, 0, 0), (0, 0, 0), (-0.01, 0, 0), (0.01, 0, 0))
+
+
+@pytest.mark.parametrize("kernel", [lb.KERNEL_TWOPASS, lb.KERNEL_FUSED])
+@pytest.mark.parametrize("storage", [W.F64, W.F32])
+def test_sheared_channel_with_droplets(storage, kernel):
+    # walls at z sliding at -+0.01 along x (the sheared channel of Sec. 5),
+    # resting walls at y, periodic x; droplets with near-contact
+    w = W.two_droplets(n=(48, 20, 18), R=5, gap=2.0, A=0.01, nc_strength=0.03, nc_range=2)
+    w.params["bc"] = (0, 1, 1)
+    w.params["wall_velocity"] = SHEAR
+    _parity(w, storage, 60, kernel)
+
+
+def test_sheared_channel_16bit():
+    w = W.two_droplets(n=(48, 20, 18), R=5, gap=2.0, A=0.01, nc_strength=0.03, nc_range=2)
+    w.params["bc"] = (0, 1, 1)
+    w.params["wall_velocity"] = SHEAR
+    _parity(w, W.F16, 60)
+
+
+def test_couette_on_gpu_is_linear():
+    H, U = 16, 0.01
+    w = W.shear_wave(L=H, U=0.0, tau_r=0.8, tau_b=0.8, red_fraction=1.0)
+    p = dict(w.params, bc=(0, 1, 0), storage=W.F64)
+    p["wall_velocity"] = ((0, 0, 0), (0, 0, 0), (-U, 0, 0), (U, 0, 0), (0, 0, 0), (0, 0, 0))
+    with lb.Lattice(p) as L:
+        L.init(w.rho_r, w.rho_b).step(6000)
+        rr, rb, j = L.moments()
+    ux = (j[0] / (rr + rb))[0, :, 0]
+    y = np.arange(H)
+    assert np.abs(ux - (-U + 2 * U * (y + 0.5) / H)).max() < 1e-12

@@ -1,0 +1,84 @@
+"""Physics of the GPU path in every storage form.
+
+- plane Poiseuille flow (walls in y, body force along x) at tau = 1/2 + sqrt(3)/4,
+  where halfway bounce-back with the exact-difference force reproduces the
+  parabola to round-off: relative L2 error of the physical velocity
+  (j + F/2)/rho against u(y) = g/(2 nu) (y + 1/2)(H - 1/2 - y);
+  gates: FP64 1e-10, FP32 1e-4, fp16 moment-split 1e-3, bf16 5e-3;
+- Laplace's law for static 3-D droplets R = 8, 10, 12: the pressure jump
+  p_in - p_out (p = rho/3) of each 16-bit form within 2 % of the FP32 jump, and
+  the FP32 jumps consistent with dp = 2 sigma / R (dp R constant within 5 %);
+- the microfluidic-crystal channel (walls, body force, near-contact) in FP32
+  and 16-bit against the FP64 GPU run.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2005_12764_amd import lb
+from paper_2005_12764_amd import workloads as W
+from tests.helpers import state_errors
+
+pytestmark = pytest.mark.gpu
+
+POIS_TOL = {W.F64: 1e-10, W.F32: 1e-4, W.F16: 1e-3, W.BF16: 5e-3}
+
+
+@pytest.mark.parametrize("storage", [W.F64, W.F32, W.F16, W.BF16])
+def test_poiseuille_channel(storage):
+    H, g = 32, 1e-6
+    tau = 0.5 + math.sqrt(3) / 4
+    nu = (tau - 0.5) / 3
+    w = W.channel(H=H, nx=4, nz=4, force=g, tau=tau, storage=storage)
+    with lb.Lattice(dict(w.params, storage=storage)) as L:
+        L.init(w.rho_r, w.rho_b)
+        L.step(int(8 * H * H / nu))
+        rr, rb, j = L.moments()
+    ux = ((j[0] + g / 2) / (rr + rb)).mean(axis=(0, 2))
+    y = np.arange(H)
+    ua = g / (2 * nu) * (y + 0.5) * (H - 0.5 - y)
+    err = float(np.linalg.norm(ux - ua) / np.linalg.norm(ua))
+    print("poiseuille storage=%d L2 error %.3e" % (storage, err), flush=True)
+    assert err <= POIS_TOL[storage]
+
+
+def _pressure_jump(storage, R, n=48, A=0.01, tau=1.0, steps=3000):
+    w = W.sphere(n=n, R=R, A=A, tau=tau, storage=storage)
+    with lb.Lattice(dict(w.params, storage=storage)) as L:
+        L.init(w.rho_r, w.rho_b).step(steps)
+        rr, rb, _ = L.moments()
+    rho, phi = rr + rb, (rr - rb) / (rr + rb)
+    c = (n - 1) / 2
+    z, y, x = np.mgrid[0:n, 0:n, 0:n]
+    r = np.sqrt((x - c) ** 2 + (y - c) ** 2 + (z - c) ** 2)
+    Rm = (3 * (phi > 0).sum() / (4 * math.pi)) ** (1 / 3)
+    return Rm, (rho[r < Rm - 3].mean() - rho[r > Rm + 3].mean()) / 3.0
+
+
+def test_laplace_law_all_storage():
+    radii = (8, 10, 12)
+    ref = {R: _pressure_jump(W.F32, R) for R in radii}
+    sig = [dp * Rm / 2 for Rm, dp in ref.values()]
+    print("laplace f32 sigma(R)", sig, "2 A tau / 9 =", 2 * 0.01 / 9, flush=True)
+    assert max(sig) / min(sig) < 1.05
+    for storage in (W.F16, W.BF16):
+        for R in radii:
+            Rm, dp = _pressure_jump(storage, R)
+            rel = abs(dp / ref[R][1] - 1)
+            print("laplace storage=%d R=%d dp %.4e (f32 %.4e) rel %.2e" % (storage, R, dp, ref[R][1], rel),
+                  flush=True)
+            assert rel <= 0.02
+
+
+def test_crystal_channel_against_fp64():
+    w = W.crystal_channel(seed=0, steps=400)
+    out = {}
+    for storage in (W.F64, W.F32, W.F16, W.BF16):
+        with lb.Lattice(dict(w.params, storage=storage)) as L:
+            L.init(w.rho_r, w.rho_b).step(w.steps)
+            out[storage] = L.state()
+    for storage, tol in ((W.F32, 1e-5), (W.F16, 1e-3), (W.BF16, 5e-3)):
+        e = state_errors(out[storage], out[W.F64])
+        print("crystal channel %d steps storage=%d vs fp64: %s" % (w.steps, storage, e), flush=True)
+        assert e["worst"] <= tol

@@ -115,3 +115,36 @@ def test_near_contact_merging_regimes():
     assert mid_off > 0.9 and mid_weak > 0.9              # the film drains: droplets merged
     assert mid_strong < -0.9                             # film stabilised, no merging
     assert np.abs(j.sum(axis=(1, 2, 3))).max() < 1e-12   # mirror-symmetric pair: no net push
+
+
+def test_couette_flow_between_sliding_walls():
+    # walls at y = -1/2 and H - 1/2 sliding at -U and +U along x (the sheared
+    # channel of Sec. 5): the steady profile is exactly linear, for a mixture too
+    H, U = 16, 0.01
+    for red in (1.0, 0.4):
+        w = W.shear_wave(L=H, U=0.0, tau_r=0.8, tau_b=1.1, red_fraction=red)
+        p = dict(w.params, bc=(0, 1, 0))
+        p["wall_velocity"] = ((0, 0, 0), (0, 0, 0), (-U, 0, 0), (U, 0, 0), (0, 0, 0), (0, 0, 0))
+        prm = oracle_params(p)
+        f = O.step(prm, O.init(prm, w.rho_r, w.rho_b), 6000)
+        rr, rb, j = O.moments(prm, f)
+        ux = (j[0] / (rr + rb))[0, :, 0]
+        y = np.arange(H)
+        ua = -U + 2 * U * (y + 0.5) / H
+        assert np.abs(ux - ua).max() < 1e-12
+        r0, b0, _ = O.moments(prm, O.init(prm, w.rho_r, w.rho_b))
+        assert abs(rr.sum() / r0.sum() - 1) < 1e-12 and (red == 1.0 or abs(rb.sum() / b0.sum() - 1) < 1e-12)
+
+
+def test_sliding_walls_conserve_colour_with_droplets():
+    w = W.two_droplets(n=(40, 20, 8), R=5, gap=3.0, A=0.01)
+    p = dict(w.params, bc=(0, 1, 0))
+    p["wall_velocity"] = ((0, 0, 0), (0, 0, 0), (-0.01, 0, 0), (0.01, 0, 0), (0, 0, 0), (0, 0, 0))
+    prm = oracle_params(p)
+    f0 = O.init(prm, w.rho_r, w.rho_b)
+    f = O.step(prm, f0, 200)
+    r0, b0, _ = O.moments(prm, f0)
+    r1, b1, j1 = O.moments(prm, f)
+    assert abs(r1.sum() / r0.sum() - 1) < 1e-12 and abs(b1.sum() / b0.sum() - 1) < 1e-12
+    # the walls drag the fluid: positive x-momentum near the top wall, negative near the bottom
+    assert j1[0][:, -1, :].mean() > 0 > j1[0][:, 0, :].mean()
