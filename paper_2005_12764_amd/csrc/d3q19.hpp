@@ -60,39 +60,55 @@ struct Coeffs {
 // Outputs of one site's collision that the 16-bit storage keeps per site.
 template <typename R>
 struct SiteTotals {
-    R rho, ux, uy, uz;     // post-collision density and velocity (j + F)/rho
+    R drho, ux, uy, uz;    // post-collision density - 1 and velocity (j + F)/rho
     R xr;                  // red fraction rho_r/rho
     R vx, vy, vz;          // recolouring vector beta (rho_r rho_b/rho) G/|G|
 };
 
-// Local collision of one site.  fr/fb hold the pulled (post-streaming)
-// populations on entry and the post-collision, recoloured populations on exit.
-// (gx,gy,gz) is the colour gradient at the site, (Fx,Fy,Fz) the total force.
+// Local collision of one site, in shifted variables: t_i = f^r_i + f^b_i - w_i
+// (the total's deviation from the rest equilibrium at unit density) and
+// d_i = f^r_i - f^b_i (the colour difference).  Carrying the small t_i keeps
+// FP32 rounding relative to the deviations that hold the flow, not to the
+// O(w_i) populations (a per-step force increment is ~1e-7 of those).
+// t/d hold the pulled (post-streaming) values on entry and the post-collision,
+// recoloured values on exit.  (gx,gy,gz) is the colour gradient at the site,
+// (Fx,Fy,Fz) the total force.
 template <typename R>
-__device__ __forceinline__ void collide(R (&fr)[Q], R (&fb)[Q], R gx, R gy, R gz, R Fx, R Fy,
-                                        R Fz, const Coeffs<R>& c, SiteTotals<R>* tot = nullptr) {
+__device__ __forceinline__ void collide(R (&t)[Q], R (&d)[Q], R gx, R gy, R gz, R Fx, R Fy, R Fz,
+                                        const Coeffs<R>& c, SiteTotals<R>* tot = nullptr) {
     using L = Lattice;
-    R rr = R(0), rb = R(0), jx = R(0), jy = R(0), jz = R(0);
+    R drho = R(0), dif = R(0), rc = R(0), jx = R(0), jy = R(0), jz = R(0);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        rr += fr[i];
-        rb += fb[i];
-        const R t = fr[i] + fb[i];
-        if (L::cx[i]) jx += L::cx[i] > 0 ? t : -t;
-        if (L::cy[i]) jy += L::cy[i] > 0 ? t : -t;
-        if (L::cz[i]) jz += L::cz[i] > 0 ? t : -t;
+        drho += t[i];
+        dif += d[i];
+        rc += weight<R>(i) + t[i];
+        if (L::cx[i]) jx += L::cx[i] > 0 ? t[i] : -t[i];
+        if (L::cy[i]) jy += L::cy[i] > 0 ? t[i] : -t[i];
+        if (L::cz[i]) jz += L::cz[i] > 0 ? t[i] : -t[i];
     }
-    const R rho = rr + rb;
+    const R rho = R(1) + drho;            // sum of the weights is 1
+    // The colour split uses rc = sum_i (w_i + t_i), rounded term by term as
+    // the colour difference is: a pure component (d_i = +-(w_i + t_i)) then
+    // gives phi = +-1 and rho_b or rho_r = 0 exactly, and stays pure.
+    const R rr = R(0.5) * (rc + dif), rb = R(0.5) * (rc - dif);
+    const R inv_rc = R(1) / rc;
     const R inv_rho = R(1) / rho;
     const R ux = jx * inv_rho, uy = jy * inv_rho, uz = jz * inv_rho;
-    // exact-difference velocity shift: F^k/rho_k with F^k = (rho_k/rho) F
-    const R vx = ux + Fx * inv_rho, vy = uy + Fy * inv_rho, vz = uz + Fz * inv_rho;
-    const R xr = rr * inv_rho, xb = rb * inv_rho;
+    // exact-difference velocity shift du = F^k/rho_k with F^k = (rho_k/rho) F
+    const R dx = Fx * inv_rho, dy = Fy * inv_rho, dz = Fz * inv_rho;
+    const R vx = ux + dx, vy = uy + dy, vz = uz + dz;
+    // s = u + (u + du): f^eq(u + du) - f^eq(u) = rho_k w_i [3 c.du + 4.5 (c.du)(c.s)
+    // - 1.5 du.s], without subtracting two equilibria
+    const R sx = ux + vx, sy = uy + vy, sz = uz + vz;
+    const R ds = dx * sx + dy * sy + dz * sz;
+    // divided, not multiplied by 1/rc, so that x_r, phi are exactly 1 there
+    const R xr = rr / rc, xb = rb / rc;
+    const R phi = dif / rc;               // x_r - x_b
     // mixture relaxation: 1/nu_bar = x_r/nu_r + x_b/nu_b, w = 2 cs2/(2 nu_bar + cs2)
     const R nubar = R(1) / (xr * c.inv_nu_r + xb * c.inv_nu_b);
     const R omega = R(2) / (R(6) * nubar + R(1));
     const R uu = ux * ux + uy * uy + uz * uz;
-    const R vv = vx * vx + vy * vy + vz * vz;
 
     const R g2 = gx * gx + gy * gy + gz * gz;
     const R gm = sqrt(g2);
@@ -100,26 +116,31 @@ __device__ __forceinline__ void collide(R (&fr)[Q], R (&fb)[Q], R gx, R gy, R gz
     const R inv_gm = has_n ? R(1) / gm : R(0);
     // perturbation amplitude (A/2)|G| and recolouring strength beta rho_r rho_b / rho
     const R pa = has_n ? c.half_A * gm : R(0);
-    const R seg = has_n ? c.beta * rr * rb * inv_rho : R(0);
+    const R seg = has_n ? c.beta * rr * rb * inv_rc : R(0);
     const R nx = gx * inv_gm, ny = gy * inv_gm, nz = gz * inv_gm;
 
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const R w = weight<R>(i);
         const R cu = R(L::cx[i]) * ux + R(L::cy[i]) * uy + R(L::cz[i]) * uz;
-        const R cv = R(L::cx[i]) * vx + R(L::cy[i]) * vy + R(L::cz[i]) * vz;
-        const R e = w * (R(1) + R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu);   // f^eq/rho_k at u
-        const R es = w * (R(1) + R(3) * cv + R(4.5) * cv * cv - R(1.5) * vv);  // at u + F/rho
-        const R pr = fr[i] - omega * (fr[i] - rr * e) + rr * (es - e);
-        const R pb = fb[i] - omega * (fb[i] - rb * e) + rb * (es - e);
+        const R cd = R(L::cx[i]) * dx + R(L::cy[i]) * dy + R(L::cz[i]) * dz;
+        const R cs = R(L::cx[i]) * sx + R(L::cy[i]) * sy + R(L::cz[i]) * sz;
+        const R q = R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu;                // f^eq/(w rho) - 1
+        const R de = w * (R(3) * cd + R(4.5) * cd * cs - R(1.5) * ds);        // source / rho_k
+        // total: BGK toward rho w (1 + q) (deviation w (drho + rho q)) plus rho de
+        const R teq = w * (drho + rho * q);
+        const R tp = t[i] - omega * (t[i] - teq) + rho * de;
+        // (the components' own relaxation only enters through this total:
+        // recolouring redistributes the colour from rho_r/rho and f*)
         const R cn = R(L::cx[i]) * nx + R(L::cy[i]) * ny + R(L::cz[i]) * nz;   // c_i . n
-        const R fs = pr + pb + pa * (w * cn * cn - bpert<R>(i));
+        const R ts = tp + pa * (w * cn * cn - bpert<R>(i));                    // perturbation
+        // recolouring: f^r = x_r f* + rec, f^b = x_b f* - rec, f* = w + t*
         const R rec = seg * w * cn * inv_clen<R>(i);
-        fr[i] = xr * fs + rec;
-        fb[i] = xb * fs - rec;
+        t[i] = ts;
+        d[i] = phi * (w + ts) + R(2) * rec;
     }
     if (tot) {
-        tot->rho = rho;
+        tot->drho = drho;
         tot->ux = vx;  // (j + F)/rho
         tot->uy = vy;
         tot->uz = vz;
@@ -128,6 +149,19 @@ __device__ __forceinline__ void collide(R (&fr)[Q], R (&fb)[Q], R gx, R gy, R gz
         tot->vy = seg * ny;
         tot->vz = seg * nz;
     }
+}
+
+// Shifted variables from the two components and back.
+template <typename R>
+__device__ __forceinline__ void to_shifted(int i, R fr, R fb, R& t, R& d) {
+    t = (fr + fb) - weight<R>(i);
+    d = fr - fb;
+}
+template <typename R>
+__device__ __forceinline__ void from_shifted(int i, R t, R d, R& fr, R& fb) {
+    const R f = weight<R>(i) + t;
+    fr = R(0.5) * (f + d);
+    fb = R(0.5) * (f - d);
 }
 
 // Equilibrium divided by the density, for the 16-bit codec and init.

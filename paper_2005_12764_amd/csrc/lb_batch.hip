@@ -530,6 +530,7 @@ static int batch_admit(lb_batch_t* b, const lb_params* params, int64_t steps, in
     if (params->storage != b->storage) return bfail(LB_EINVAL, "job storage differs from the batch storage");
     const int K = params->nc_strength > 0.0 ? params->nc_range : 0;
     if (K + 1 > kBatchH) return bfail(LB_EINVAL, "batched jobs support near-contact ranges up to 2");
+    if (make_geom(*params).moving) return bfail(LB_EINVAL, "batched jobs do not support moving walls");
     if (steps < 0) return bfail(LB_EINVAL, "steps must be >= 0");
     int s = -1;
     for (int k = 0; k < b->max_jobs; ++k)

@@ -80,8 +80,17 @@ __device__ __forceinline__ void load_rec_plane(const Geom& g, const Src& src, co
         const int xx = halo_coord(x0 - 1 + lx, g.nx, g.wx);
         const int yy = halo_coord(y0 - 1 + ly, g.ny, g.wy);
         const size_t s = (size_t)site_of(g, xx, yy, zz);
-        dstp[2 * k] = *reinterpret_cast<const f4*>(src.rec + 8 * s);
-        dstp[2 * k + 1] = *reinterpret_cast<const f4*>(src.rec + 8 * s + 4);
+        const f4 a = *reinterpret_cast<const f4*>(src.rec + 8 * s);
+        const f4 b = *reinterpret_cast<const f4*>(src.rec + 8 * s + 4);
+#if LB_RING_SOA
+        float* pf = reinterpret_cast<float*>(dstp);
+        const int stride = rr.LY * LX;
+        pf[k] = a.x; pf[stride + k] = a.y; pf[2 * stride + k] = a.z; pf[3 * stride + k] = a.w;
+        pf[4 * stride + k] = b.x; pf[5 * stride + k] = b.y; pf[6 * stride + k] = b.z; pf[7 * stride + k] = b.w;
+#else
+        dstp[2 * k] = a;
+        dstp[2 * k + 1] = b;
+#endif
     }
 }
 
@@ -158,6 +167,8 @@ __device__ __forceinline__ void fused_tile(const Geom& g, const Src& src, const 
     const int tid = threadIdx.x;
     const int nt = blockDim.x;
     const bool use_ring = Src::ring && phi_in != nullptr;
+    Src srcr = src;
+    if constexpr (Src::ring) srcr.ring_plane_floats = rr.LY * RecRing<TX>::LX * 8;
     for (int p = za - H; p < zb + H; ++p) {
         const int slot = (p - (za - H)) % NP;
         // ---- phase field of plane p on the tile and its halo
@@ -173,15 +184,9 @@ __device__ __forceinline__ void fused_tile(const Geom& g, const Src& src, const 
                     dstp[q] = phi_in[s];
                     continue;
                 }
-                R fr[Q], fb[Q];
-                src.pull(g, s, xx, yy, zz, fr, fb);
-                R a = R(0), b = R(0);
-#pragma unroll
-                for (int i = 0; i < Q; ++i) {
-                    a += fr[i];
-                    b += fb[i];
-                }
-                dstp[q] = (a - b) / (a + b);
+                R t[Q], d[Q];
+                src.pull(g, s, xx, yy, zz, t, d);
+                dstp[q] = phase_of(t, d);
             }
         }
         if constexpr (Src::ring) {
@@ -200,17 +205,17 @@ __device__ __forceinline__ void fused_tile(const Geom& g, const Src& src, const 
                 const int x = x0 + tx, y = y0 + ty;
                 if (x >= g.nx || y >= g.ny) continue;
                 const int s = site_of(g, x, y, cz);
-                R fr[Q], fb[Q];
+                R t[Q], d[Q];
                 if constexpr (Src::ring) {
                     if (use_ring) {
                         const f4* const planes[3] = {rr.plane((cz - za) % 3), rr.plane((cz - za + 1) % 3),
                                                      rr.plane((cz - za + 2) % 3)};
-                        src.pull_ring(g, s, x, y, cz, fr, fb, planes, ty + 1, tx + 1, RecRing<TX>::LX);
+                        srcr.pull_ring(g, s, x, y, cz, t, d, planes, ty + 1, tx + 1, RecRing<TX>::LX);
                     } else {
-                        src.pull(g, s, x, y, cz, fr, fb);
+                        src.pull(g, s, x, y, cz, t, d);
                     }
                 } else {
-                    src.pull(g, s, x, y, cz, fr, fb);
+                    src.pull(g, s, x, y, cz, t, d);
                 }
                 const int ly = ty + H, lx = tx + H;
                 R gx, gy, gz;
@@ -219,8 +224,8 @@ __device__ __forceinline__ void fused_tile(const Geom& g, const Src& src, const 
                 if (H > 1 && c.nc_range > 0)
                     ring_near_contact<R, TX, H>(g, ring, s0, x, y, cz, ly, lx, gx, gy, gz, c, Fx, Fy, Fz);
                 SiteTotals<R> tot;
-                collide<R>(fr, fb, gx, gy, gz, Fx, Fy, Fz, c, &tot);
-                dst.store(s, fr, fb, tot);
+                collide<R>(t, d, gx, gy, gz, Fx, Fy, Fz, c, &tot);
+                dst.store(s, t, d, tot);
             }
         }
         __syncthreads();
@@ -236,6 +241,8 @@ __device__ __forceinline__ void phase_tile(const Geom& g, const Src& src, R* __r
     const int tid = threadIdx.x;
     const int nt = blockDim.x;
     if constexpr (Src::ring) {
+        Src srcr = src;
+        srcr.ring_plane_floats = rr.LY * RecRing<TX>::LX * 8;
         for (int q = za - 1; q <= zb; ++q) {
             load_rec_plane<Src, TX>(g, src, rr, (q - za + 1) % 3, x0, y0, q);
             __syncthreads();
@@ -248,15 +255,9 @@ __device__ __forceinline__ void phase_tile(const Geom& g, const Src& src, R* __r
                     const int x = x0 + tx, y = y0 + ty;
                     if (x >= g.nx || y >= g.ny) continue;
                     const int s = site_of(g, x, y, cz);
-                    R fr[Q], fb[Q];
-                    src.pull_ring(g, s, x, y, cz, fr, fb, planes, ty + 1, tx + 1, RecRing<TX>::LX);
-                    R a = R(0), b = R(0);
-#pragma unroll
-                    for (int i = 0; i < Q; ++i) {
-                        a += fr[i];
-                        b += fb[i];
-                    }
-                    phi[s] = (a - b) / (a + b);
+                    R t[Q], d[Q];
+                    srcr.pull_ring(g, s, x, y, cz, t, d, planes, ty + 1, tx + 1, RecRing<TX>::LX);
+                    phi[s] = phase_of(t, d);
                 }
             }
             __syncthreads();
@@ -268,15 +269,9 @@ __device__ __forceinline__ void phase_tile(const Geom& g, const Src& src, R* __r
                 const int x = x0 + tx, y = y0 + ty;
                 if (x >= g.nx || y >= g.ny) continue;
                 const int s = site_of(g, x, y, cz);
-                R fr[Q], fb[Q];
-                src.pull(g, s, x, y, cz, fr, fb);
-                R a = R(0), b = R(0);
-#pragma unroll
-                for (int i = 0; i < Q; ++i) {
-                    a += fr[i];
-                    b += fb[i];
-                }
-                phi[s] = (a - b) / (a + b);
+                R t[Q], d[Q];
+                src.pull(g, s, x, y, cz, t, d);
+                phi[s] = phase_of(t, d);
             }
     }
 }

@@ -92,56 +92,60 @@ __device__ __forceinline__ double wall_term(const Geom& g, int i, int x, int y, 
 // site's post-collision populations in place (aligned, coalesced).
 // ---------------------------------------------------------------------------
 
-// Raw populations [2][19][N] of type T.
-template <typename T>
+// Raw storage [2][19][N] of type T in shifted variables: component 0 holds
+// t_i = f^r_i + f^b_i - w_i, component 1 holds d_i = f^r_i - f^b_i.  MW: the
+// lattice has moving walls (a separate instantiation, so resting-wall kernels
+// carry none of that code).
+template <typename T, bool MW = false>
 struct RawPop {
     T* f;
     size_t N;
 
     template <typename R>
-    __device__ __forceinline__ void pull(const Geom& g, int s, int x, int y, int z, R (&fr)[Q],
-                                         R (&fb)[Q]) const {
+    __device__ __forceinline__ void pull(const Geom& g, int s, int x, int y, int z, R (&t)[Q],
+                                         R (&d)[Q]) const {
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            int d;
-            const int src = pull_source(g, i, x, y, z, s, d);
-            fr[i] = R(f[(size_t)d * N + src]);
-            fb[i] = R(f[(size_t)(Q + d) * N + src]);
+            int dir;
+            const int src = pull_source(g, i, x, y, z, s, dir);
+            t[i] = R(f[(size_t)dir * N + src]);
+            d[i] = R(f[(size_t)(Q + dir) * N + src]);
         }
-        if (g.moving) add_wall_terms<R>(g, s, x, y, z, fr, fb);
+        if constexpr (MW) {
+            if (g.moving) add_wall_terms<R>(g, s, x, y, z, t, d);
+        }
     }
 
-    // Moving-wall terms of the reflected directions, shared by the site's own
-    // post-collision colour fraction.
+    // Moving-wall terms of the reflected directions, shared between the
+    // components by the site's own post-collision rho_k/rho.
     template <typename R>
-    __device__ void add_wall_terms(const Geom& g, int s, int x, int y, int z, R (&fr)[Q], R (&fb)[Q]) const {
-        R a = R(0), b = R(0);
+    __device__ void add_wall_terms(const Geom& g, int s, int x, int y, int z, R (&t)[Q], R (&d)[Q]) const {
+        R st = R(0), sd = R(0);
         bool have = false;
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
-            int d;
-            (void)pull_source(g, i, x, y, z, s, d);
-            if (d == i) continue;
+            int dir;
+            (void)pull_source(g, i, x, y, z, s, dir);
+            if (dir == i) continue;
             if (!have) {
                 for (int j = 0; j < Q; ++j) {
-                    a += R(f[(size_t)j * N + s]);
-                    b += R(f[(size_t)(Q + j) * N + s]);
+                    st += weight<R>(j) + R(f[(size_t)j * N + s]);
+                    sd += R(f[(size_t)(Q + j) * N + s]);
                 }
                 have = true;
             }
             const R add = R(wall_term(g, i, x, y, z));
-            const R xr = a / (a + b);
-            fr[i] += add * xr;
-            fb[i] += add * (R(1) - xr);
+            t[i] += add;
+            d[i] += add * (sd / st);   // add x_r - add x_b
         }
     }
     template <typename R>
-    __device__ __forceinline__ void store(int s, const R (&fr)[Q], const R (&fb)[Q],
+    __device__ __forceinline__ void store(int s, const R (&t)[Q], const R (&d)[Q],
                                           const SiteTotals<R>&) const {
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            __builtin_nontemporal_store(T(fr[i]), &f[(size_t)i * N + s]);
-            __builtin_nontemporal_store(T(fb[i]), &f[(size_t)(Q + i) * N + s]);
+            __builtin_nontemporal_store(T(t[i]), &f[(size_t)i * N + s]);
+            __builtin_nontemporal_store(T(d[i]), &f[(size_t)(Q + i) * N + s]);
         }
     }
     static constexpr bool needs_totals = false;
@@ -169,7 +173,10 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 // (8 floats each) live at once, ~200 VGPRs and two waves per SIMD; with
 // groups of 5 the step kernels fit in ~116 VGPRs.
 #ifndef LB_DECODE_GROUP
-#define LB_DECODE_GROUP 5
+#define LB_DECODE_GROUP 19
+#endif
+#ifndef LB_RING_SOA
+#define LB_RING_SOA 0
 #endif
 constexpr int kDecodeGroup = LB_DECODE_GROUP;
 
@@ -180,26 +187,28 @@ __device__ __forceinline__ void pin_group(int last, R (&fr)[Q], R (&fb)[Q]) {
 }
 
 // 16-bit moment-split storage.  Per site, 8 FP32 values rec[N][8] (two
-// 16-byte vectors per site): density,
+// 16-byte vectors per site): density - 1,
 // velocity (3), red fraction, recolouring vector (3) of the post-collision
 // state; per direction dev[19][N]: the total post-collision population minus
 // its equilibrium rho f^eq_unit(u), times `scale`, in 16 bits.  The red part
 // of direction i is x_r f*_i + w_i (c_i . v)/|c_i|, which is exactly the form
-// recolouring produces, so colour is carried in FP32.
-template <typename H>
+// recolouring produces, so colour is carried in FP32.  MW as for RawPop.
+template <typename H, bool MW = false>
 struct SplitPop {
     float* rec;
     H* dev;
     size_t N;
     float scale, inv_scale;
+    int ring_plane_floats;  // floats per record-ring plane (for the SoA ring layout)
 
     // Decode direction i (read as d = i, or opp(i) after a bounce-back) from
-    // the source's record (ra, rb) and its 16-bit deviation.
+    // the source's record (ra, rb) and its 16-bit deviation, into the shifted
+    // variables t_i = f*_i - w_i and d_i = f^r_i - f^b_i.
     template <typename R>
-    __device__ __forceinline__ void decode(int i, int d, const f4& ra, const f4& rb, H dv16, R& fr_i,
-                                           R& fb_i) const {
+    __device__ __forceinline__ void decode(int i, int d, const f4& ra, const f4& rb, H dv16, R& t_i,
+                                           R& d_i) const {
         using L = Lattice;
-        const float rho = ra.x, ux = ra.y, uy = ra.z, uz = ra.w;
+        const float drho = ra.x, ux = ra.y, uy = ra.z, uz = ra.w;
         const float xr = rb.x, vx = rb.y, vy = rb.z, vz = rb.w;
         const float dv = Half<H>::to_f(dv16) * inv_scale;
         // direction d is i, or its opposite after a bounce-back (same shell)
@@ -209,10 +218,11 @@ struct SplitPop {
         const float uu = ux * ux + uy * uy + uz * uz;
         const float w = weight<float>(i);
         const float ic = inv_clen<float>(i);
-        const float fs = rho * (w * (1.0f + 3.0f * cu + 4.5f * cu * cu - 1.5f * uu)) + dv;
-        const float r = xr * fs + w * (cdx * vx + cdy * vy + cdz * vz) * ic;
-        fr_i = R(r);
-        fb_i = R(fs - r);
+        const float q = 3.0f * cu + 4.5f * cu * cu - 1.5f * uu;
+        const float tt = w * (drho + (1.0f + drho) * q) + dv;      // rho w (1 + q) - w + dev
+        const float dd = (2.0f * xr - 1.0f) * (w + tt) + 2.0f * w * (cdx * vx + cdy * vy + cdz * vz) * ic;
+        t_i = R(tt);
+        d_i = R(dd);
     }
 
     template <typename R>
@@ -227,22 +237,24 @@ struct SplitPop {
             decode<R>(i, d, ra, rb, dev[(size_t)d * N + src], fr[i], fb[i]);
             if (i % kDecodeGroup == kDecodeGroup - 1 || i == Q - 1) pin_group(i, fr, fb);
         }
-        if (g.moving) add_wall_terms<R>(g, s, x, y, z, rec[8 * (size_t)s + 4], fr, fb);
+        if constexpr (MW) {
+            if (g.moving) add_wall_terms<R>(g, s, x, y, z, rec[8 * (size_t)s + 4], fr, fb);
+        }
     }
 
     // Moving-wall terms of the reflected directions, shared by the site's own
     // post-collision red fraction xr (from its record).
     template <typename R>
-    __device__ void add_wall_terms(const Geom& g, int s, int x, int y, int z, float xr, R (&fr)[Q],
-                                   R (&fb)[Q]) const {
+    __device__ void add_wall_terms(const Geom& g, int s, int x, int y, int z, float xr, R (&t)[Q],
+                                   R (&d)[Q]) const {
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
-            int d;
-            (void)pull_source(g, i, x, y, z, s, d);
-            if (d == i) continue;
+            int dir;
+            (void)pull_source(g, i, x, y, z, s, dir);
+            if (dir == i) continue;
             const R add = R(wall_term(g, i, x, y, z));
-            fr[i] += add * R(xr);
-            fb[i] += add * (R(1) - R(xr));
+            t[i] += add;
+            d[i] += add * (R(2) * R(xr) - R(1));
         }
     }
 
@@ -262,26 +274,47 @@ struct SplitPop {
             const bool bb = (d != i);
             const f4* pl = bb ? ring[1] : ring[1 - L::cz[i]];
             const int pos = bb ? (ly * LXR + lx) : ((ly - L::cy[i]) * LXR + lx - L::cx[i]);
+#if LB_RING_SOA
+            // ring plane = 8 float arrays of LY*LXR entries (plane stride passed via LXR * LYR)
+            const float* pf = reinterpret_cast<const float*>(pl);
+            const int stride = ring_plane_floats / 8;
+            const f4 ra = {pf[pos], pf[stride + pos], pf[2 * stride + pos], pf[3 * stride + pos]};
+            const f4 rb = {pf[4 * stride + pos], pf[5 * stride + pos], pf[6 * stride + pos], pf[7 * stride + pos]};
+            decode<R>(i, d, ra, rb, dev[(size_t)d * N + src], fr[i], fb[i]);
+#else
             decode<R>(i, d, pl[2 * pos], pl[2 * pos + 1], dev[(size_t)d * N + src], fr[i], fb[i]);
+#endif
             if (i % kDecodeGroup == kDecodeGroup - 1 || i == Q - 1) pin_group(i, fr, fb);
         }
-        if (g.moving) add_wall_terms<R>(g, s, x, y, z, ring[1][2 * (ly * LXR + lx) + 1].x, fr, fb);
+        if constexpr (MW) {
+#if LB_RING_SOA
+            const float xr_own = reinterpret_cast<const float*>(ring[1])[4 * (ring_plane_floats / 8) + ly * LXR + lx];
+#else
+            const float xr_own = ring[1][2 * (ly * LXR + lx) + 1].x;
+#endif
+            if (g.moving) add_wall_terms<R>(g, s, x, y, z, xr_own, fr, fb);
+        }
     }
 
     template <typename R>
-    __device__ __forceinline__ void store(int s, const R (&fr)[Q], const R (&fb)[Q],
-                                          const SiteTotals<R>& t) const {
-        const float rho = float(t.rho), ux = float(t.ux), uy = float(t.uy), uz = float(t.uz);
-        const f4 ra = {rho, ux, uy, uz};
-        const f4 rb = {float(t.xr), float(t.vx), float(t.vy), float(t.vz)};
+    __device__ __forceinline__ void store(int s, const R (&t)[Q], const R (&d)[Q],
+                                          const SiteTotals<R>& tot) const {
+        const float drho = float(tot.drho), ux = float(tot.ux), uy = float(tot.uy), uz = float(tot.uz);
+        const f4 ra = {drho, ux, uy, uz};
+        const f4 rb = {float(tot.xr), float(tot.vx), float(tot.vy), float(tot.vz)};
         __builtin_nontemporal_store(ra, reinterpret_cast<f4*>(rec + 8 * (size_t)s));
         __builtin_nontemporal_store(rb, reinterpret_cast<f4*>(rec + 8 * (size_t)s + 4));
+        const float uu = ux * ux + uy * uy + uz * uz;
+        using L = Lattice;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            const float fs = float(fr[i]) + float(fb[i]);
-            const float e = rho * feq_unit<float>(i, ux, uy, uz);
-            dev[(size_t)i * N + s] = Half<H>::from_f((fs - e) * scale);
+            const float cu = float(L::cx[i]) * ux + float(L::cy[i]) * uy + float(L::cz[i]) * uz;
+            const float q = 3.0f * cu + 4.5f * cu * cu - 1.5f * uu;
+            // f*_i - rho w (1 + q) = t_i - w (drho + rho q)
+            const float dv = float(t[i]) - weight<float>(i) * (drho + (1.0f + drho) * q);
+            dev[(size_t)i * N + s] = Half<H>::from_f(dv * scale);
         }
+        (void)d;
     }
     static constexpr bool needs_totals = true;
     static constexpr bool ring = true;
@@ -298,8 +331,8 @@ template <typename S>
 struct Occupancy {
     static constexpr int waves = 1;
 };
-template <typename H>
-struct Occupancy<SplitPop<H>> {
+template <typename H, bool MW>
+struct Occupancy<SplitPop<H, MW>> {
     static constexpr int waves = LB_SPLIT_WAVES;
 };
 template <typename A, typename B>
@@ -374,6 +407,20 @@ __device__ __forceinline__ void near_contact(const Geom& g, const R* __restrict_
 // Two-pass step.
 // ---------------------------------------------------------------------------
 
+// phi = (rho_r - rho_b)/rho = sum_i d_i / sum_i (w_i + t_i), the density
+// summed as the collision sums it for the colour split (exactly +-1 in a
+// pure component).
+template <typename R>
+__device__ __forceinline__ R phase_of(const R (&t)[Q], const R (&d)[Q]) {
+    R rc = R(0), sd = R(0);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        rc += weight<R>(i) + t[i];
+        sd += d[i];
+    }
+    return sd / rc;
+}
+
 // Pass 1: phi = (rho_r - rho_b)/rho of the post-streaming state.
 template <typename R, typename Src>
 __global__ __launch_bounds__(256, Occupancy<Src>::waves) void phase_kernel(Geom g, Src src, R* __restrict__ phi) {
@@ -381,15 +428,9 @@ __global__ __launch_bounds__(256, Occupancy<Src>::waves) void phase_kernel(Geom 
     if (s >= g.N) return;
     int x, y, z;
     site_xyz(g, s, x, y, z);
-    R fr[Q], fb[Q];
-    src.pull(g, s, x, y, z, fr, fb);
-    R rr = R(0), rb = R(0);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        rr += fr[i];
-        rb += fb[i];
-    }
-    phi[s] = (rr - rb) / (rr + rb);
+    R t[Q], d[Q];
+    src.pull(g, s, x, y, z, t, d);
+    phi[s] = phase_of(t, d);
 }
 
 // Pass 2: pull, colour gradient, near-contact, collision, store.
@@ -400,15 +441,15 @@ __global__ __launch_bounds__(256, (waves_of<Src, Dst>())) void collide_kernel(Ge
     if (s >= g.N) return;
     int x, y, z;
     site_xyz(g, s, x, y, z);
-    R fr[Q], fb[Q];
-    src.pull(g, s, x, y, z, fr, fb);
+    R t[Q], d[Q];
+    src.pull(g, s, x, y, z, t, d);
     R gx, gy, gz;
     gradient<R>(g, phi, x, y, z, gx, gy, gz);
     R Fx = c.fx, Fy = c.fy, Fz = c.fz;
     if (c.nc_range > 0 && c.nc_strength != R(0)) near_contact<R>(g, phi, x, y, z, gx, gy, gz, c, Fx, Fy, Fz);
     SiteTotals<R> tot;
-    collide<R>(fr, fb, gx, gy, gz, Fx, Fy, Fz, c, &tot);
-    dst.store(s, fr, fb, tot);
+    collide<R>(t, d, gx, gy, gz, Fx, Fy, Fz, c, &tot);
+    dst.store(s, t, d, tot);
 }
 
 // ---------------------------------------------------------------------------
@@ -441,14 +482,14 @@ __global__ __launch_bounds__(256) void init_raw_kernel(Geom g, T* __restrict__ f
             uy = double(u[N + t]);
             uz = double(u[2 * N + t]);
         }
-        double e;
-        {
-            const double cu = L::cx[d] * ux + L::cy[d] * uy + L::cz[d] * uz;
-            const double uu = ux * ux + uy * uy + uz * uz;
-            e = weight<double>(d) * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
-        }
-        f[(size_t)j * N + s] = T(double(rr[t]) * e);
-        f[(size_t)(Q + j) * N + s] = T(double(rb[t]) * e);
+        // f^eq_d(rho_k, u) = rho_k w (1 + q): t = w (rho - 1 + rho q), d = (rho_r - rho_b) w (1 + q)
+        const double cu = L::cx[d] * ux + L::cy[d] * uy + L::cz[d] * uz;
+        const double uu = ux * ux + uy * uy + uz * uz;
+        const double q = 3.0 * cu + 4.5 * cu * cu - 1.5 * uu;
+        const double w = weight<double>(d);
+        const double a = double(rr[t]), b = double(rb[t]);
+        f[(size_t)j * N + s] = T(w * ((a + b - 1.0) + (a + b) * q));
+        f[(size_t)(Q + j) * N + s] = T((a - b) * w * (1.0 + q));
     }
 }
 
@@ -471,8 +512,9 @@ __global__ __launch_bounds__(256) void import_raw_kernel(Geom g, T* __restrict__
         const int zt = L::cz[j] ? step_back(z, -L::cz[j], g.nz, g.wz, bb) : z;
         const int t = bb ? s : site_of(g, xt, yt, zt);
         const int d = bb ? L::opp[j] : j;
-        f[(size_t)j * N + s] = T(fin[(size_t)d * N + t]);
-        f[(size_t)(Q + j) * N + s] = T(fin[(size_t)(Q + d) * N + t]);
+        const double a = double(fin[(size_t)d * N + t]), b = double(fin[(size_t)(Q + d) * N + t]);
+        f[(size_t)j * N + s] = T((a + b) - weight<double>(d));
+        f[(size_t)(Q + j) * N + s] = T(a - b);
     }
 }
 
@@ -483,13 +525,17 @@ __global__ __launch_bounds__(256) void export_kernel(Geom g, Src src, Out* __res
     if (s >= g.N) return;
     int x, y, z;
     site_xyz(g, s, x, y, z);
-    R fr[Q], fb[Q];
-    src.pull(g, s, x, y, z, fr, fb);
+    // decoded in FP64 whatever the storage, so that f^r + f^b - w and
+    // f^r - f^b of the export reproduce the stored values
+    double t[Q], d[Q];
+    src.pull(g, s, x, y, z, t, d);
     const size_t N = (size_t)g.N;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        out[(size_t)i * N + s] = Out(fr[i]);
-        out[(size_t)(Q + i) * N + s] = Out(fb[i]);
+        double fr, fb;
+        from_shifted<double>(i, t[i], d[i], fr, fb);
+        out[(size_t)i * N + s] = Out(fr);
+        out[(size_t)(Q + i) * N + s] = Out(fb);
     }
 }
 
@@ -502,18 +548,18 @@ __global__ __launch_bounds__(256) void moments_kernel(Geom g, Src src, Out* rr_o
     if (s >= g.N) return;
     int x, y, z;
     site_xyz(g, s, x, y, z);
-    R fr[Q], fb[Q];
-    src.pull(g, s, x, y, z, fr, fb);
-    R rr = R(0), rb = R(0), jx = R(0), jy = R(0), jz = R(0);
+    R t[Q], d[Q];
+    src.pull(g, s, x, y, z, t, d);
+    R st = R(0), sd = R(0), jx = R(0), jy = R(0), jz = R(0);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        rr += fr[i];
-        rb += fb[i];
-        const R t = fr[i] + fb[i];
-        if (L::cx[i]) jx += L::cx[i] > 0 ? t : -t;
-        if (L::cy[i]) jy += L::cy[i] > 0 ? t : -t;
-        if (L::cz[i]) jz += L::cz[i] > 0 ? t : -t;
+        st += t[i];
+        sd += d[i];
+        if (L::cx[i]) jx += L::cx[i] > 0 ? t[i] : -t[i];
+        if (L::cy[i]) jy += L::cy[i] > 0 ? t[i] : -t[i];
+        if (L::cz[i]) jz += L::cz[i] > 0 ? t[i] : -t[i];
     }
+    const R rr = R(0.5) * (R(1) + st + sd), rb = R(0.5) * (R(1) + st - sd);
     const size_t N = (size_t)g.N;
     if (rr_out) rr_out[s] = Out(rr);
     if (rb_out) rb_out[s] = Out(rb);
@@ -609,18 +655,19 @@ __global__ __launch_bounds__(256) void totals_kernel(Geom g, Src src, Neu* __res
     for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < g.N; s += gridDim.x * blockDim.x) {
         int x, y, z;
         site_xyz(g, s, x, y, z);
-        R fr[Q], fb[Q];
-        src.pull(g, s, x, y, z, fr, fb);
-        double rr = 0, rb = 0, jx = 0, jy = 0, jz = 0;
+        R t[Q], d[Q];
+        src.pull(g, s, x, y, z, t, d);
+        double st = 0, sd = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            rr += double(fr[i]);
-            rb += double(fb[i]);
-            const double t = double(fr[i]) + double(fb[i]);
-            if (L::cx[i]) jx += L::cx[i] > 0 ? t : -t;
-            if (L::cy[i]) jy += L::cy[i] > 0 ? t : -t;
-            if (L::cz[i]) jz += L::cz[i] > 0 ? t : -t;
+            st += double(t[i]);
+            sd += double(d[i]);
+            const double ti = double(t[i]);
+            if (L::cx[i]) jx += L::cx[i] > 0 ? ti : -ti;
+            if (L::cy[i]) jy += L::cy[i] > 0 ? ti : -ti;
+            if (L::cz[i]) jz += L::cz[i] > 0 ? ti : -ti;
         }
+        const double rr = 0.5 * (1.0 + st + sd), rb = 0.5 * (1.0 + st - sd);
         const double rho = rr + rb;
         const bool bad = !(rho > 0.0) || !isfinite(rho) || !isfinite(jx) || !isfinite(jy) ||
                          !isfinite(jz);

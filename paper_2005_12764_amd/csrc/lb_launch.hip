@@ -28,9 +28,9 @@ int launch_status(const char* what) {
 
 unsigned grid_for(int N) { return (unsigned)((N + kBlock - 1) / kBlock); }
 
-template <typename H>
-SplitPop<H> split_view(void* buf, size_t N, int scale_log2) {
-    SplitPop<H> s;
+template <typename H, bool MW = false>
+SplitPop<H, MW> split_view(void* buf, size_t N, int scale_log2) {
+    SplitPop<H, MW> s;
     s.rec = (float*)buf;
     s.dev = (H*)((float*)buf + 8 * N);
     s.N = N;
@@ -41,21 +41,28 @@ SplitPop<H> split_view(void* buf, size_t N, int scale_log2) {
 }
 
 // Calls fn(R{}, src, coeffs) with the compute type and a view of the current
-// state in its storage.
-template <typename Fn>
-int with_state(const LatticeView& v, Fn&& fn) {
+// state in its storage; lattices with moving walls get the storage types that
+// add the moving-wall terms (a raw initial state is never pulled with them).
+template <bool MW, typename Fn>
+int with_state_mw(const LatticeView& v, Fn&& fn) {
     const size_t N = (size_t)v.g.N;
     switch (v.p->storage) {
-        case LB_STORE_F64: return fn(double(0), RawPop<double>{(double*)v.cur, N}, v.cd);
-        case LB_STORE_F32: return fn(float(0), RawPop<float>{(float*)v.cur, N}, v.cf);
+        case LB_STORE_F64: return fn(double(0), RawPop<double, MW>{(double*)v.cur, N}, v.cd);
+        case LB_STORE_F32: return fn(float(0), RawPop<float, MW>{(float*)v.cur, N}, v.cf);
         case LB_STORE_F16:
             if (v.pending) return fn(float(0), RawPop<float>{(float*)v.pending, N}, v.cf);
-            return fn(float(0), split_view<__half>(v.cur, N, v.p->scale_log2), v.cf);
+            return fn(float(0), split_view<__half, MW>(v.cur, N, v.p->scale_log2), v.cf);
         case LB_STORE_BF16:
             if (v.pending) return fn(float(0), RawPop<float>{(float*)v.pending, N}, v.cf);
-            return fn(float(0), split_view<__hip_bfloat16>(v.cur, N, v.p->scale_log2), v.cf);
+            return fn(float(0), split_view<__hip_bfloat16, MW>(v.cur, N, v.p->scale_log2), v.cf);
     }
     return set_error(LB_EINVAL, "unknown storage");
+}
+
+template <typename Fn>
+int with_state(const LatticeView& v, Fn&& fn) {
+    if (v.g.moving) return with_state_mw<true>(v, fn);
+    return with_state_mw<false>(v, fn);
 }
 
 int max_lds_bytes() {
@@ -220,12 +227,12 @@ int choose_kernel(const lb_params& p) {
 // raw FP32 initial state of a 16-bit lattice into its moment-split storage.
 template <typename Src, typename Dst>
 struct StepPair : std::false_type {};
-template <typename T>
-struct StepPair<RawPop<T>, RawPop<T>> : std::true_type {};
+template <typename T, bool MW>
+struct StepPair<RawPop<T, MW>, RawPop<T>> : std::true_type {};
 template <typename H>
 struct StepPair<RawPop<float>, SplitPop<H>> : std::true_type {};
-template <typename H>
-struct StepPair<SplitPop<H>, SplitPop<H>> : std::true_type {};
+template <typename H, bool MW>
+struct StepPair<SplitPop<H, MW>, SplitPop<H>> : std::true_type {};
 
 template <typename Dst>
 int step_into(const LatticeView& v, int kernel, const Dst& dst, const StepEvents* t) {

@@ -178,10 +178,11 @@ def test_state_roundtrip_and_checkpoint_resume():
         B.load_raw(ck)
         B.step(10)
         assert np.array_equal(B.state(np.float32), straight)
-        # export -> import -> export is exact for raw storage
+        # export -> import -> export: storage holds t = f^r + f^b - w and
+        # d = f^r - f^b, so the round trip costs a few FP32 roundings
         s = A.state(np.float64)
         A.set_state(s)
-        assert np.array_equal(A.state(np.float64), s)
+        assert np.abs(A.state(np.float64) - s).max() <= 2e-7
 
 
 @pytest.mark.parametrize("storage", [W.F32, W.F16])
