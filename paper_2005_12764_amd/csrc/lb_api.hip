@@ -120,7 +120,10 @@ struct lb_t {
     int device;
     void* buf[2];      // post-collision populations, ping-pong
     void* pending;     // raw FP32 state of a 16-bit lattice before its first step
-    void* phi;         // phase field (double for F64, float otherwise)
+    void* phi;         // phase field of the two-pass step (double for F64, float otherwise)
+    void* part[2];     // own phase sums of the single-pass step, ping-pong
+    int part_cur;      // part[part_cur] belongs to the current state ...
+    bool part_valid;   // ... when this is set
     Neu* partial;      // reduction partials
     double* dtot;      // device totals [14]
     int cur;           // buffer holding the current state
@@ -144,6 +147,9 @@ lbm::LatticeView view_of(lb_t* h) {
     v.nxt = h->buf[h->cur ^ 1];
     v.pending = h->pending;
     v.phi = h->phi;
+    v.part_in = h->part[h->part_cur];
+    v.part_out = h->part[h->part_cur ^ 1];
+    v.part_valid = h->part_valid;
     v.cd = h->cd;
     v.cf = h->cf;
     return v;
@@ -155,6 +161,8 @@ void release(lb_t* h) {
     if (h->buf[1]) (void)hipFree(h->buf[1]);
     if (h->pending) (void)hipFree(h->pending);
     if (h->phi) (void)hipFree(h->phi);
+    if (h->part[0]) (void)hipFree(h->part[0]);
+    if (h->part[1]) (void)hipFree(h->part[1]);
     if (h->partial) (void)hipFree(h->partial);
     if (h->dtot) (void)hipFree(h->dtot);
     delete h;
@@ -180,7 +188,11 @@ int64_t lb_footprint_bytes(const lb_params* p) {
     std::string why;
     if (validate_params(p, why) != LB_OK) return -1;
     const size_t N = size_t(p->nx) * p->ny * p->nz;
-    size_t b = 2 * pop_bytes(p->storage, N) + N * (p->storage == LB_STORE_F64 ? 8 : 4);
+    const size_t real = p->storage == LB_STORE_F64 ? 8 : 4;
+    size_t b = 2 * pop_bytes(p->storage, N) + N * real;
+    // phase sums of the one-read step (raw storage unless two passes are asked
+    // for; an upper bound for lattices the automatic choice steps otherwise)
+    if (p->storage <= LB_STORE_F32 && p->kernel != LB_KERNEL_TWOPASS) b += 2 * 2 * N * real;
     return (int64_t)b;
 }
 
@@ -215,6 +227,14 @@ int lb_create(const lb_params* params, void* hip_stream, lb_t** out) {
         (rc = check_hip(hipMalloc((void**)&h->dtot, sizeof(double) * 2 * NTOT), "hipMalloc totals"))) {
         release(h);
         return rc;
+    }
+    if (h->kernel == LB_KERNEL_FUSED) {
+        const size_t pbytes = 2 * N * (h->p.storage == LB_STORE_F64 ? 8 : 4);
+        if ((rc = check_hip(hipMalloc(&h->part[0], pbytes), "hipMalloc phase sums")) ||
+            (rc = check_hip(hipMalloc(&h->part[1], pbytes), "hipMalloc phase sums"))) {
+            release(h);
+            return rc;
+        }
     }
     *out = h;
     return LB_OK;
@@ -268,6 +288,7 @@ int lb_init_fields(lb_t* h, const void* rho_r, const void* rho_b, const void* u,
     if (rc) return rc;
     h->initialised = true;
     h->fresh = true;
+    h->part_valid = false;
     h->steps = 0;
     return LB_OK;
 }
@@ -307,7 +328,35 @@ int lb_init_droplets(lb_t* h, const double* centres, const double* radii, int32_
     if (rc) return rc;
     h->initialised = true;
     h->fresh = true;
+    h->part_valid = false;
     h->steps = 0;
+    return LB_OK;
+}
+
+// One step of lattice h (events t may be null); `used` receives the kernel
+// that ran.  Lattices with moving walls step with two passes (the single
+// pass carries no wall terms).
+static int advance(lb_t* h, const StepEvents* t, int* used) {
+    LatticeView v = view_of(h);
+    const int kernel = (h->kernel == LB_KERNEL_FUSED && v.g.moving) ? LB_KERNEL_TWOPASS : h->kernel;
+    int rc = launch_step(v, kernel, t);
+    if (rc) return rc;
+    if (h->pending) {
+        // the first step consumed the raw initial state
+        (void)hipStreamSynchronize(h->stream);
+        (void)hipFree(h->pending);
+        h->pending = nullptr;
+    }
+    h->cur ^= 1;
+    h->steps++;
+    h->fresh = false;
+    if (kernel == LB_KERNEL_FUSED) {
+        h->part_cur ^= 1;
+        h->part_valid = true;
+    } else {
+        h->part_valid = false;
+    }
+    if (used) *used = kernel;
     return LB_OK;
 }
 
@@ -316,18 +365,8 @@ int lb_step(lb_t* h, int32_t n) {
     if (n < 0) return fail(LB_EINVAL, "n must be >= 0");
     if (!h->initialised) return fail(LB_ESTATE, "lb_step before lb_init_fields");
     for (int32_t k = 0; k < n; ++k) {
-        LatticeView v = view_of(h);
-        int rc = launch_step(v, h->kernel);
+        int rc = advance(h, nullptr, nullptr);
         if (rc) return rc;
-        if (h->pending) {
-            // the first step consumed the raw initial state
-            (void)hipStreamSynchronize(h->stream);
-            (void)hipFree(h->pending);
-            h->pending = nullptr;
-        }
-        h->cur ^= 1;
-        h->steps++;
-        h->fresh = false;
     }
     return LB_OK;
 }
@@ -342,26 +381,18 @@ int lb_step_timed(lb_t* h, int32_t n, double kernel_ms[3]) {
     int made = 0;
     for (; made < n && !rc; ++made)
         for (int k = 0; k < 3 && !rc; ++k) rc = check_hip(hipEventCreate(&ev[made].ev[k]), "hipEventCreate");
-    for (int32_t k = 0; k < n && !rc; ++k) {
-        LatticeView v = view_of(h);
-        rc = launch_step(v, h->kernel, &ev[k]);
-        if (rc) break;
-        if (h->pending) {
-            (void)hipStreamSynchronize(h->stream);
-            (void)hipFree(h->pending);
-            h->pending = nullptr;
-        }
-        h->cur ^= 1;
-        h->steps++;
-        h->fresh = false;
-    }
+    int* used = new (std::nothrow) int[n]();
+    if (!used) rc = fail(LB_ENOMEM, "host allocation failed");
+    for (int32_t k = 0; k < n && !rc; ++k) rc = advance(h, &ev[k], &used[k]);
     if (!rc) rc = check_hip(hipStreamSynchronize(h->stream), "sync");
     double a = 0, b = 0, c = 0;
     if (!rc) {
         for (int32_t k = 0; k < n; ++k) {
+            // two-pass: [0] phase pass, [1] collide pass; single pass: [0] the
+            // phase sums of a state no single pass produced, [1] the pass
             float t01 = 0, t12 = 0, t02 = 0;
-            if (h->kernel == LB_KERNEL_TWOPASS) (void)hipEventElapsedTime(&t01, ev[k].ev[0], ev[k].ev[1]);
-            (void)hipEventElapsedTime(&t12, h->kernel == LB_KERNEL_TWOPASS ? ev[k].ev[1] : ev[k].ev[0], ev[k].ev[2]);
+            (void)hipEventElapsedTime(&t01, ev[k].ev[0], ev[k].ev[1]);
+            (void)hipEventElapsedTime(&t12, ev[k].ev[1], ev[k].ev[2]);
             (void)hipEventElapsedTime(&t02, ev[k].ev[0], ev[k].ev[2]);
             a += t01;
             b += t12;
@@ -375,6 +406,7 @@ int lb_step_timed(lb_t* h, int32_t n, double kernel_ms[3]) {
         for (int e = 0; e < 3; ++e)
             if (ev[k].ev[e]) (void)hipEventDestroy(ev[k].ev[e]);
     delete[] ev;
+    delete[] used;
     return rc;
 }
 
@@ -471,6 +503,7 @@ int lb_set_state(lb_t* h, const void* f, int32_t dtype, int32_t on_device) {
     if (rc) return rc;
     h->initialised = true;
     h->fresh = true;
+    h->part_valid = false;
     return LB_OK;
 }
 
@@ -502,6 +535,7 @@ int lb_load_raw(lb_t* h, const void* src, int32_t on_device) {
     }
     h->initialised = true;
     h->fresh = false;
+    h->part_valid = false;
     return LB_OK;
 }
 

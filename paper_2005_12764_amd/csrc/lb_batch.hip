@@ -547,7 +547,7 @@ static int batch_admit(lb_batch_t* b, const lb_params* params, int64_t steps, in
     h = HostJob();
     h.p = *params;
     if (h.p.scale_log2 == 0) h.p.scale_log2 = 16;
-    h.p.kernel = LB_KERNEL_FUSED;
+    h.p.kernel = LB_KERNEL_TWOPASS;
     h.off = off;
     h.bytes = bytes;
     h.cd = make_coeffs<double>(h.p);
@@ -563,9 +563,11 @@ static int batch_admit(lb_batch_t* b, const lb_params* params, int64_t steps, in
         if (!rc) {
             LatticeView v = job_view(b, s, b0, b1, b->staging);
             v.g.moving = 0;  // the first step reads the initial, not collided, state
+            v.phi = b1 + job_half(b->storage, N);  // the job's phase field
             rc = init(b, v, ctx);
             if (!rc && steps > 0) {
-                rc = launch_step(v, LB_KERNEL_FUSED, nullptr);
+                // first step from the raw FP32 initial state into 16-bit storage
+                rc = launch_step(v, LB_KERNEL_TWOPASS, nullptr);
                 done = 1;
             }
         }

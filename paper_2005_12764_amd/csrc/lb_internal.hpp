@@ -5,8 +5,7 @@
 #include <string>
 
 #include "lb.h"
-#include "lb_fused.hpp"
-#include "lb_kernels.hpp"
+#include "lb_single.hpp"
 
 namespace lbm {
 
@@ -16,13 +15,16 @@ constexpr int kTotalsBlocks = 512;
 
 // What a launch needs to know about one lattice.
 struct LatticeView {
-    const lb_params* p;
+    const lb_params* p = nullptr;
     Geom g;
-    hipStream_t stream;
-    void* cur;      // post-collision buffer holding the current state
-    void* nxt;      // buffer the next step writes
-    void* pending;  // raw FP32 current state of a 16-bit lattice (else null)
-    void* phi;      // phase-field scratch
+    hipStream_t stream = nullptr;
+    void* cur = nullptr;       // post-collision buffer holding the current state
+    void* nxt = nullptr;       // buffer the next step writes
+    void* pending = nullptr;   // raw FP32 current state of a 16-bit lattice (else null)
+    void* phi = nullptr;       // phase-field scratch of the two-pass step
+    void* part_in = nullptr;   // own phase sums of the current state (single pass)
+    void* part_out = nullptr;  // own phase sums the single pass writes for the next state
+    bool part_valid = false;   // part_in holds the current state's sums
     Coeffs<double> cd;
     Coeffs<float> cf;
 };
@@ -36,7 +38,7 @@ size_t pop_bytes(int storage, size_t N);
 
 // Tile kernels: 64-wide tiles of TY rows marching z-chunks of TZ planes.
 constexpr int kTX = 64;
-enum TileKind { TILE_COLLIDE = 0, TILE_FUSED = 1, TILE_PHASE = 2 };
+enum TileKind { TILE_COLLIDE = 0, TILE_SINGLE = 1, TILE_PHASE = 2 };
 int env_int(const char* name, int dflt);
 int tile_halo(const lb_params& p);
 size_t tile_lds(const lb_params& p, int kind, int TY);

@@ -116,6 +116,14 @@ struct RawPop {
         }
     }
 
+    // Direction i of a pull whose source() gave (src, dir); no wall terms.
+    template <typename R>
+    __device__ __forceinline__ void pull_one(int i, int src, int dir, R& t, R& d) const {
+        (void)i;
+        t = R(f[(size_t)dir * N + src]);
+        d = R(f[(size_t)(Q + dir) * N + src]);
+    }
+
     // Moving-wall terms of the reflected directions, shared between the
     // components by the site's own post-collision rho_k/rho.
     template <typename R>
@@ -148,8 +156,19 @@ struct RawPop {
             __builtin_nontemporal_store(T(d[i]), &f[(size_t)(Q + i) * N + s]);
         }
     }
+    // Store, and replace t, d by the values a later pull reads.
+    template <typename R>
+    __device__ __forceinline__ void store_as_read(int s, R (&t)[Q], R (&d)[Q], const SiteTotals<R>& tot) const {
+        store(s, t, d, tot);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            t[i] = R(T(t[i]));
+            d[i] = R(T(d[i]));
+        }
+    }
     static constexpr bool needs_totals = false;
     static constexpr bool ring = false;
+    static constexpr bool moving = MW;
 };
 
 template <typename H>
@@ -167,23 +186,21 @@ struct Half<__hip_bfloat16> {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-// The 16-bit pull decodes directions in groups and pins each group's decoded
-// values in registers (an empty asm with the values as operands, no code)
-// before the next group: otherwise the compiler keeps all 19 source records
-// (8 floats each) live at once, ~200 VGPRs and two waves per SIMD; with
-// groups of 5 the step kernels fit in ~116 VGPRs.
-#ifndef LB_DECODE_GROUP
-#define LB_DECODE_GROUP 19
-#endif
 #ifndef LB_RING_SOA
 #define LB_RING_SOA 0
 #endif
-constexpr int kDecodeGroup = LB_DECODE_GROUP;
 
-template <typename R>
-__device__ __forceinline__ void pin_group(int last, R (&fr)[Q], R (&fb)[Q]) {
-#pragma unroll
-    for (int j = last - (last % kDecodeGroup); j <= last; ++j) asm volatile("" : "+v"(fr[j]), "+v"(fb[j]));
+// c_d . a for d = i (sg = 1) or its opposite (sg = -1), summed x, y, z from
+// the non-zero components only, so that a value and its reflected reading
+// round identically.
+__device__ __forceinline__ float cdot(int i, float sg, float ax, float ay, float az) {
+    using L = Lattice;
+    float v = 0.0f;
+    bool any = false;
+    if (L::cx[i]) { v = L::cx[i] > 0 ? ax : -ax; any = true; }
+    if (L::cy[i]) { const float b = L::cy[i] > 0 ? ay : -ay; v = any ? v + b : b; any = true; }
+    if (L::cz[i]) { const float b = L::cz[i] > 0 ? az : -az; v = any ? v + b : b; }
+    return sg * v;
 }
 
 // 16-bit moment-split storage.  Per site, 8 FP32 values rec[N][8] (two
@@ -201,45 +218,59 @@ struct SplitPop {
     float scale, inv_scale;
     int ring_plane_floats;  // floats per record-ring plane (for the SoA ring layout)
 
-    // Decode direction i (read as d = i, or opp(i) after a bounce-back) from
-    // the source's record (ra, rb) and its 16-bit deviation, into the shifted
-    // variables t_i = f*_i - w_i and d_i = f^r_i - f^b_i.
+    // Equilibrium excess of direction i (read as d = i, sg = 1, or as its
+    // opposite after a bounce-back, sg = -1) from the source record ra:
+    // X = drho + rho q(u), so that f*_i - w_i = w_i X + deviation.  Fused
+    // multiply-adds are written out so that every reading of a stored value,
+    // and the store's own reading, rounds the same way.
+    static __device__ __forceinline__ float excess(int i, float sg, const f4& ra) {
+        const float drho = ra.x, ux = ra.y, uy = ra.z, uz = ra.w;
+        const float cu = cdot(i, sg, ux, uy, uz);
+        const float uu = __builtin_fmaf(ux, ux, __builtin_fmaf(uy, uy, uz * uz));
+        const float q = __builtin_fmaf(cu, __builtin_fmaf(4.5f, cu, 3.0f), -1.5f * uu);
+        return __builtin_fmaf(1.0f + drho, q, drho);
+    }
+    // Shifted variables t_i = f*_i - w_i and d_i = f^r_i - f^b_i from the
+    // excess X, the 16-bit deviation and the colour part of the record rb.
+    __device__ __forceinline__ void finish(int i, float sg, float X, const f4& rb, H dv16, float& tt,
+                                           float& dd) const {
+        const float w = weight<float>(i);
+        tt = __builtin_fmaf(w, X, Half<H>::to_f(dv16) * inv_scale);
+        const float cv = cdot(i, sg, rb.y, rb.z, rb.w);
+        dd = __builtin_fmaf(2.0f * rb.x - 1.0f, w + tt, (2.0f * w * inv_clen<float>(i)) * cv);
+    }
     template <typename R>
     __device__ __forceinline__ void decode(int i, int d, const f4& ra, const f4& rb, H dv16, R& t_i,
                                            R& d_i) const {
-        using L = Lattice;
-        const float drho = ra.x, ux = ra.y, uy = ra.z, uz = ra.w;
-        const float xr = rb.x, vx = rb.y, vy = rb.z, vz = rb.w;
-        const float dv = Half<H>::to_f(dv16) * inv_scale;
-        // direction d is i, or its opposite after a bounce-back (same shell)
         const float sg = (d == i) ? 1.0f : -1.0f;
-        const float cdx = sg * float(L::cx[i]), cdy = sg * float(L::cy[i]), cdz = sg * float(L::cz[i]);
-        const float cu = cdx * ux + cdy * uy + cdz * uz;
-        const float uu = ux * ux + uy * uy + uz * uz;
-        const float w = weight<float>(i);
-        const float ic = inv_clen<float>(i);
-        const float q = 3.0f * cu + 4.5f * cu * cu - 1.5f * uu;
-        const float tt = w * (drho + (1.0f + drho) * q) + dv;      // rho w (1 + q) - w + dev
-        const float dd = (2.0f * xr - 1.0f) * (w + tt) + 2.0f * w * (cdx * vx + cdy * vy + cdz * vz) * ic;
+        float tt, dd;
+        finish(i, sg, excess(i, sg, ra), rb, dv16, tt, dd);
         t_i = R(tt);
         d_i = R(dd);
     }
 
     template <typename R>
-    __device__ __forceinline__ void pull(const Geom& g, int s, int x, int y, int z, R (&fr)[Q],
-                                         R (&fb)[Q]) const {
+    __device__ __forceinline__ void pull(const Geom& g, int s, int x, int y, int z, R (&t)[Q],
+                                         R (&d_)[Q]) const {
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             int d;
             const int src = pull_source(g, i, x, y, z, s, d);
             const f4 ra = *reinterpret_cast<const f4*>(rec + 8 * (size_t)src);
             const f4 rb = *reinterpret_cast<const f4*>(rec + 8 * (size_t)src + 4);
-            decode<R>(i, d, ra, rb, dev[(size_t)d * N + src], fr[i], fb[i]);
-            if (i % kDecodeGroup == kDecodeGroup - 1 || i == Q - 1) pin_group(i, fr, fb);
+            decode<R>(i, d, ra, rb, dev[(size_t)d * N + src], t[i], d_[i]);
         }
         if constexpr (MW) {
-            if (g.moving) add_wall_terms<R>(g, s, x, y, z, rec[8 * (size_t)s + 4], fr, fb);
+            if (g.moving) add_wall_terms<R>(g, s, x, y, z, rec[8 * (size_t)s + 4], t, d_);
         }
+    }
+
+    // Direction i of a pull whose source() gave (src, dir); no wall terms.
+    template <typename R>
+    __device__ __forceinline__ void pull_one(int i, int src, int dir, R& t, R& d) const {
+        const f4 ra = *reinterpret_cast<const f4*>(rec + 8 * (size_t)src);
+        const f4 rb = *reinterpret_cast<const f4*>(rec + 8 * (size_t)src + 4);
+        decode<R>(i, dir, ra, rb, dev[(size_t)dir * N + src], t, d);
     }
 
     // Moving-wall terms of the reflected directions, shared by the site's own
@@ -263,8 +294,8 @@ struct SplitPop {
     // `ring[k]` points at the plane of z - 1 + k, (ly, lx) is the site's
     // position in the ring plane, LXR its row length.
     template <typename R>
-    __device__ __forceinline__ void pull_ring(const Geom& g, int s, int x, int y, int z, R (&fr)[Q],
-                                              R (&fb)[Q], const f4* const (&ring)[3], int ly, int lx,
+    __device__ __forceinline__ void pull_ring(const Geom& g, int s, int x, int y, int z, R (&t)[Q],
+                                              R (&d_)[Q], const f4* const (&ring)[3], int ly, int lx,
                                               int LXR) const {
         using L = Lattice;
 #pragma unroll
@@ -280,11 +311,10 @@ struct SplitPop {
             const int stride = ring_plane_floats / 8;
             const f4 ra = {pf[pos], pf[stride + pos], pf[2 * stride + pos], pf[3 * stride + pos]};
             const f4 rb = {pf[4 * stride + pos], pf[5 * stride + pos], pf[6 * stride + pos], pf[7 * stride + pos]};
-            decode<R>(i, d, ra, rb, dev[(size_t)d * N + src], fr[i], fb[i]);
+            decode<R>(i, d, ra, rb, dev[(size_t)d * N + src], t[i], d_[i]);
 #else
-            decode<R>(i, d, pl[2 * pos], pl[2 * pos + 1], dev[(size_t)d * N + src], fr[i], fb[i]);
+            decode<R>(i, d, pl[2 * pos], pl[2 * pos + 1], dev[(size_t)d * N + src], t[i], d_[i]);
 #endif
-            if (i % kDecodeGroup == kDecodeGroup - 1 || i == Q - 1) pin_group(i, fr, fb);
         }
         if constexpr (MW) {
 #if LB_RING_SOA
@@ -292,32 +322,43 @@ struct SplitPop {
 #else
             const float xr_own = ring[1][2 * (ly * LXR + lx) + 1].x;
 #endif
-            if (g.moving) add_wall_terms<R>(g, s, x, y, z, xr_own, fr, fb);
+            if (g.moving) add_wall_terms<R>(g, s, x, y, z, xr_own, t, d_);
         }
     }
 
     template <typename R>
     __device__ __forceinline__ void store(int s, const R (&t)[Q], const R (&d)[Q],
                                           const SiteTotals<R>& tot) const {
-        const float drho = float(tot.drho), ux = float(tot.ux), uy = float(tot.uy), uz = float(tot.uz);
-        const f4 ra = {drho, ux, uy, uz};
+        R tc[Q], dc[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            tc[i] = t[i];
+            dc[i] = d[i];
+        }
+        store_as_read(s, tc, dc, tot);
+    }
+    // Store, and replace t, d by the values a later pull decodes (exactly).
+    template <typename R>
+    __device__ __forceinline__ void store_as_read(int s, R (&t)[Q], R (&d)[Q], const SiteTotals<R>& tot) const {
+        const f4 ra = {float(tot.drho), float(tot.ux), float(tot.uy), float(tot.uz)};
         const f4 rb = {float(tot.xr), float(tot.vx), float(tot.vy), float(tot.vz)};
         __builtin_nontemporal_store(ra, reinterpret_cast<f4*>(rec + 8 * (size_t)s));
         __builtin_nontemporal_store(rb, reinterpret_cast<f4*>(rec + 8 * (size_t)s + 4));
-        const float uu = ux * ux + uy * uy + uz * uz;
-        using L = Lattice;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            const float cu = float(L::cx[i]) * ux + float(L::cy[i]) * uy + float(L::cz[i]) * uz;
-            const float q = 3.0f * cu + 4.5f * cu * cu - 1.5f * uu;
-            // f*_i - rho w (1 + q) = t_i - w (drho + rho q)
-            const float dv = float(t[i]) - weight<float>(i) * (drho + (1.0f + drho) * q);
-            dev[(size_t)i * N + s] = Half<H>::from_f(dv * scale);
+            const float X = excess(i, 1.0f, ra);
+            // deviation of f*_i - w_i = t_i from w_i X
+            const H h = Half<H>::from_f((float(t[i]) - weight<float>(i) * X) * scale);
+            dev[(size_t)i * N + s] = h;
+            float tt, dd;
+            finish(i, 1.0f, X, rb, h, tt, dd);
+            t[i] = R(tt);
+            d[i] = R(dd);
         }
-        (void)d;
     }
     static constexpr bool needs_totals = true;
     static constexpr bool ring = true;
+    static constexpr bool moving = MW;
 };
 
 // Minimum waves per SIMD the step kernels ask the compiler for, per storage.

@@ -7,8 +7,8 @@
 #include <string>
 #include <type_traits>
 
-#include "lb_fused.hpp"
 #include "lb_internal.hpp"
+#include "lb_single.hpp"
 
 namespace lbm {
 
@@ -16,6 +16,7 @@ namespace {
 
 constexpr int kBlock = 256;
 int max_lds_bytes();
+int device_lds_bytes();
 size_t real_size(const lb_params& p);
 bool split_storage(const lb_params& p);
 
@@ -65,32 +66,36 @@ int with_state(const LatticeView& v, Fn&& fn) {
     return with_state_mw<false>(v, fn);
 }
 
-int max_lds_bytes() {
+// LDS per workgroup the device allows (160 KiB on gfx950).
+int device_lds_bytes() {
     static int cached = -1;
     if (cached < 0) {
         int dev = 0, v = 0;
         (void)hipGetDevice(&dev);
         if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
             v = 65536;
-        cached = std::min(v, 65536);
+        cached = v;
     }
     return cached;
 }
+
+// Budget of the two-pass tile kernels (64 KiB: more LDS per workgroup would
+// cost them occupancy).
+int max_lds_bytes() { return std::min(device_lds_bytes(), 65536); }
 
 size_t real_size(const lb_params& p) { return p.storage == LB_STORE_F64 ? 8 : 4; }
 
 bool split_storage(const lb_params& p) { return p.storage >= LB_STORE_F16; }
 
-// z-marching tile kernel: phi_in == nullptr computes phi itself (single
-// pass), otherwise reads the phase pass's phi (collide pass of two-pass).
+// Collide pass of the two-pass step: z-marching tiles reading the phase
+// pass's phi through an LDS ring.
 template <typename R, typename Src, typename Dst, int H>
 int zmarch_h(const LatticeView& v, const Src& src, const Dst& dst, const Coeffs<R>& c, const R* phi_in) {
-    const int kind = phi_in ? TILE_COLLIDE : TILE_FUSED;
-    const FusedShape fs = tile_shape(*v.p, kind);
-    const size_t lds = tile_lds(*v.p, kind, fs.TY);
+    const FusedShape fs = tile_shape(*v.p, TILE_COLLIDE);
+    const size_t lds = tile_lds(*v.p, TILE_COLLIDE, fs.TY);
     hipLaunchKernelGGL((fused_kernel<R, Src, Dst, kTX, H>), dim3(fs.nblocks), dim3(kBlock), lds, v.stream, v.g, src,
                        dst, c, fs, phi_in);
-    return launch_status(phi_in ? "collide pass" : "fused_kernel");
+    return launch_status("collide pass");
 }
 
 template <typename R, typename Src, typename Dst>
@@ -105,13 +110,50 @@ int zmarch(const LatticeView& v, const Src& src, const Dst& dst, const Coeffs<R>
     return set_error(LB_EINVAL, "near-contact range outside the tile kernels' halo");
 }
 
-template <typename R, typename Src, typename Dst>
-int fused(const LatticeView& v, const Src& src, const Dst& dst, const Coeffs<R>& c, const StepEvents* t) {
-    if (t) {
-        (void)hipEventRecord(t->ev[0], v.stream);
-        (void)hipEventRecord(t->ev[1], v.stream);
+// Single pass: the own partial sums of the current state come from the
+// previous single-pass step, or from part_kernel when no such step made it.
+template <typename R, typename Src, typename Dst, int H>
+int single_h(const LatticeView& v, const Src& src, const Dst& dst, const Coeffs<R>& c, const FusedShape& fs) {
+    const size_t lds = tile_lds(*v.p, TILE_SINGLE, kSingleTY);
+    auto kern = single_kernel<R, Src, Dst, kTX, H>;
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return set_error(LB_EDEVICE, (std::string("single_kernel LDS: ") + hipGetErrorString(e)).c_str());
     }
-    int rc = zmarch<R>(v, src, dst, c, (const R*)nullptr);
+    hipLaunchKernelGGL(kern, dim3(fs.nblocks), dim3(kTX * kSingleTY), lds, v.stream, v.g, src, dst, c, fs,
+                       (const R*)v.phi, (Part2<R>*)v.part_out);
+    return launch_status("single_kernel");
+}
+
+template <typename R, typename Src, typename Dst>
+int single_pass(const LatticeView& v, const Src& src, const Dst& dst, const Coeffs<R>& c, const StepEvents* t) {
+    if (!v.part_in || !v.part_out || !v.phi) return set_error(LB_EINVAL, "single pass without phase buffers");
+    const FusedShape fs = tile_shape(*v.p, TILE_SINGLE);
+    if (fs.TY != kSingleTY) return set_error(LB_EINVAL, "single-pass tile does not fit in LDS");
+    if (t) (void)hipEventRecord(t->ev[0], v.stream);
+    if (!v.part_valid) {
+        hipLaunchKernelGGL((part_kernel<R, Src, kTX, kSingleTY>), dim3(grid_for(v.g.N)), dim3(kBlock), 0, v.stream,
+                           v.g, src, fs.TZ, (Part2<R>*)v.part_in);
+        int rc = launch_status("part_kernel");
+        if (rc) return rc;
+    }
+    hipLaunchKernelGGL((assemble_kernel<R, Src, kTX, kSingleTY>), dim3(grid_for(v.g.N)), dim3(kBlock), 0, v.stream,
+                       v.g, src, fs.TZ, (const Part2<R>*)v.part_in, (R*)v.phi);
+    {
+        int rc = launch_status("assemble_kernel");
+        if (rc) return rc;
+    }
+    if (t) (void)hipEventRecord(t->ev[1], v.stream);
+    int rc;
+    switch (tile_halo(*v.p)) {
+        case 1: rc = single_h<R, Src, Dst, 1>(v, src, dst, c, fs); break;
+        case 2: rc = single_h<R, Src, Dst, 2>(v, src, dst, c, fs); break;
+        case 3: rc = single_h<R, Src, Dst, 3>(v, src, dst, c, fs); break;
+        case 4: rc = single_h<R, Src, Dst, 4>(v, src, dst, c, fs); break;
+        case 5: rc = single_h<R, Src, Dst, 5>(v, src, dst, c, fs); break;
+        default: return set_error(LB_EINVAL, "near-contact range outside the tile kernels' halo");
+    }
     if (t) (void)hipEventRecord(t->ev[2], v.stream);
     return rc;
 }
@@ -137,6 +179,7 @@ int phase_pass(const LatticeView& v, const Src& src) {
 // global memory site by site).
 template <typename R, typename Src, typename Dst>
 int two_pass(const LatticeView& v, const Src& src, const Dst& dst, const Coeffs<R>& c, const StepEvents* t) {
+    if (!v.phi) return set_error(LB_EINVAL, "two-pass step without a phase-field buffer");
     if (t) (void)hipEventRecord(t->ev[0], v.stream);
     int rc = phase_pass<R>(v, src);
     if (rc) return rc;
@@ -155,7 +198,9 @@ int two_pass(const LatticeView& v, const Src& src, const Dst& dst, const Coeffs<
 template <typename R, typename Src, typename Dst>
 int step_with(const LatticeView& v, int kernel, const Src& src, const Dst& dst, const Coeffs<R>& c,
               const StepEvents* t) {
-    if (kernel == LB_KERNEL_FUSED) return fused<R>(v, src, dst, c, t);
+    if constexpr (!Src::moving) {
+        if (kernel == LB_KERNEL_FUSED) return single_pass<R>(v, src, dst, c, t);
+    }
     return two_pass<R>(v, src, dst, c, t);
 }
 
@@ -176,13 +221,15 @@ size_t tile_lds(const lb_params& p, int kind, int TY) {
     switch (kind) {
         case TILE_PHASE: return rec;
         case TILE_COLLIDE: return ((phi + 15) & ~size_t(15)) + (split ? rec : 0);
-        default: return phi;
+        default:  // TILE_SINGLE: phi ring, record ring, exchange of the c_y != 0 directions
+            return ((phi + 15) & ~size_t(15)) + (split ? rec : 0) + (size_t)2 * kXchDirs * kTX * TY * real_size(p);
     }
 }
 
 // Tile rows: preferred per kind and storage (measured on MI355X), else the
 // largest that keeps the LDS rings within the per-workgroup budget.
 int tile_rows(const lb_params& p, int kind) {
+    if (kind == TILE_SINGLE) return tile_lds(p, kind, kSingleTY) <= (size_t)device_lds_bytes() ? kSingleTY : 0;
     const char* env = kind == TILE_PHASE ? "LB_PHASE_TY" : "LB_COLLIDE_TY";
     int want = env_int(env, 0);
     if (want <= 0) {
@@ -215,12 +262,19 @@ FusedShape tile_shape(const lb_params& p, int kind, int target_blocks) {
 }
 
 int choose_kernel(const lb_params& p) {
-    const bool fits = tile_rows(p, TILE_FUSED) > 0;
+    const bool fits = tile_rows(p, TILE_SINGLE) > 0;
     if (p.kernel == LB_KERNEL_TWOPASS) return LB_KERNEL_TWOPASS;
     if (p.kernel == LB_KERNEL_FUSED) return fits ? LB_KERNEL_FUSED : -1;
-    // automatic: two passes (measured faster than the single pass on MI355X:
-    // the single pass's second read of each plane misses the caches)
-    return LB_KERNEL_TWOPASS;
+    // automatic: the one-read step for raw storage (measured faster than two
+    // passes); 16-bit storage and lattices with moving walls take two passes
+    // (the 16-bit collide is bound by its decode arithmetic, where the
+    // one-read step's extra work does not pay; moving walls need wall terms
+    // the one-read step does not carry)
+    bool moving = false;
+    for (int f = 0; f < 6; ++f)
+        for (int k = 0; k < 3; ++k) moving |= p.bc[f / 2] != 0 && p.wall_velocity[f][k] != 0.0;
+    if (split_storage(p) || moving || !fits) return LB_KERNEL_TWOPASS;
+    return LB_KERNEL_FUSED;
 }
 
 // Source/destination storage pairs a step may combine: same storage, or the

@@ -1,0 +1,353 @@
+// lb_single.hpp -- the one-read step: collide-and-stream tiles that also
+// produce the phase-field sums of the next step.
+//
+// The phase field of a site is phi = D / Rc with D = sum_i d_i and
+// Rc = sum_i (w_i + t_i) over its 19 pulled (post-streaming) populations.
+// The collide pass writes those populations and holds them in registers, so
+// each tile also sums, for every site of its own box, the terms whose source
+// lies in the same box ("own" terms): a partial (D_own, Rc_own) per site.
+// The terms whose source lies in another tile ("foreign": only sites on a
+// face of their box have any) are pulled from the population arrays by a
+// light assembly kernel that turns the partial sums into phi.  Each
+// population is read from HBM once per step (plus the few foreign ones),
+// instead of once by a phase pass and again by the collide pass.
+//
+// Summation order is fixed, so results are reproducible: the own terms of a
+// site in four groups -- sources in plane z-1, bounce-backs from the site
+// itself, in-plane sources, sources in plane z+1 -- each in ascending
+// direction; then the foreign terms face by face (z, y, x), each in
+// ascending direction.  D and Rc are summed term by term alike,
+// so a pure component (d_i = +-(w_i + t_i)) gives phi = +-1 exactly, as in
+// the collision.
+#pragma once
+#include "lb_fused.hpp"
+
+namespace lbm {
+
+// Own partial sums of one site.
+template <typename R>
+struct Part2 {
+    R dn, rc;
+};
+
+// Rows of the single-pass tile (one site per thread and plane).
+constexpr int kSingleTY = 8;
+
+// Own box of a site: its tile column [x0, x1) x [y0, y1) and z chunk [z0, z1).
+struct OwnBox {
+    int x0, x1, y0, y1, z0, z1;
+    __device__ __forceinline__ bool has(int x, int y, int z) const {
+        return x >= x0 && x < x1 && y >= y0 && y < y1 && z >= z0 && z < z1;
+    }
+};
+
+template <int TX, int TY>
+__device__ __forceinline__ OwnBox box_of(const Geom& g, int TZ, int x, int y, int z) {
+    OwnBox b;
+    b.x0 = x - x % TX;
+    b.x1 = min(b.x0 + TX, g.nx);
+    b.y0 = y - y % TY;
+    b.y1 = min(b.y0 + TY, g.ny);
+    b.z0 = z - z % TZ;
+    b.z1 = min(b.z0 + TZ, g.nz);
+    return b;
+}
+
+// Group of direction i at a destination, in summation order: 0 = source in
+// plane z-1, 1 = reflected from the site itself, 2 = in-plane source, 3 =
+// source in plane z+1.
+__device__ __forceinline__ int group_of(int i, bool reflected) {
+    return reflected ? 1 : (Lattice::cz[i] > 0 ? 0 : (Lattice::cz[i] == 0 ? 2 : 3));
+}
+
+// Own partial sums of the current state, for a state that no single-pass
+// step produced (initial, imported, or left by a two-pass step).
+template <typename R, typename Src, int TX, int TY>
+__global__ __launch_bounds__(256) void part_kernel(Geom g, Src src, int TZ, Part2<R>* __restrict__ part) {
+    using L = Lattice;
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= g.N) return;
+    int x, y, z;
+    site_xyz(g, s, x, y, z);
+    const OwnBox b = box_of<TX, TY>(g, TZ, x, y, z);
+    R dn = R(0), rc = R(0);
+#pragma unroll
+    for (int grp = 0; grp < 4; ++grp) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            int dir;
+            const int sr = pull_source(g, i, x, y, z, s, dir);
+            const bool refl = dir != i;
+            if (group_of(i, refl) != grp) continue;
+            if (!refl && !b.has(x - L::cx[i], y - L::cy[i], z - L::cz[i])) continue;
+            R t, d;
+            src.template pull_one<R>(i, sr, dir, t, d);
+            rc += weight<R>(i) + t;
+            dn += d;
+        }
+    }
+    part[s] = Part2<R>{dn, rc};
+}
+
+// Faces of a site's own box along one axis: lo = first coordinate of its
+// tile (sources at v - 1 lie outside), hi = last (sources at v + 1 outside).
+struct Faces {
+    bool lo, hi;
+};
+template <int T>
+__device__ __forceinline__ Faces faces_of(int v, int n) {
+    const int r = v % T;
+    return Faces{r == 0, r == T - 1 || v == n - 1};
+}
+__device__ __forceinline__ Faces faces_z(int v, int z0, int z1) { return Faces{v == z0, v == z1 - 1}; }
+
+// Does direction i leave the box through the faces f (c > 0 enters through
+// lo, c < 0 through hi)?
+__device__ __forceinline__ bool leaves(int c, const Faces& f) { return (c > 0 && f.lo) || (c < 0 && f.hi); }
+
+// Foreign terms of site s = (x, y, z) whose source lies outside the box
+// through the faces of `axis` (0 = x, 1 = y, 2 = z) and not through those of
+// an axis summed before it (z, then y, then x); bounce-backs are own terms.
+template <typename R, typename Src, int AXIS>
+__device__ __forceinline__ void foreign_terms(const Geom& g, const Src& src, int s, int x, int y, int z,
+                                              const Faces& fx, const Faces& fy, const Faces& fz, R& dn,
+                                              R& rc) {
+    using L = Lattice;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const bool oz = leaves(L::cz[i], fz), oy = leaves(L::cy[i], fy), ox = leaves(L::cx[i], fx);
+        const bool mine = AXIS == 2 ? oz : (AXIS == 1 ? (oy && !oz) : (ox && !oy && !oz));
+        if (!mine) continue;
+        int dir;
+        const int sr = pull_source(g, i, x, y, z, s, dir);
+        if (dir != i) continue;
+        R t, d;
+        src.template pull_one<R>(i, sr, dir, t, d);
+        rc += weight<R>(i) + t;
+        dn += d;
+    }
+}
+
+// phi of every site from the own partial sums and the foreign terms.
+template <typename R, typename Src, int TX, int TY>
+__global__ __launch_bounds__(256) void assemble_kernel(Geom g, Src src, int TZ, const Part2<R>* __restrict__ part,
+                                                       R* __restrict__ phi) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= g.N) return;
+    int x, y, z;
+    site_xyz(g, s, x, y, z);
+    const Part2<R> P = part[s];
+    R dn = P.dn, rc = P.rc;
+    const int z0 = z - z % TZ;
+    const Faces fx = faces_of<TX>(x, g.nx), fy = faces_of<TY>(y, g.ny), fz = faces_z(z, z0, min(z0 + TZ, g.nz));
+    if (fz.lo || fz.hi) foreign_terms<R, Src, 2>(g, src, s, x, y, z, fx, fy, fz, dn, rc);
+    if (fy.lo || fy.hi) foreign_terms<R, Src, 1>(g, src, s, x, y, z, fx, fy, fz, dn, rc);
+    if (fx.lo || fx.hi) foreign_terms<R, Src, 0>(g, src, s, x, y, z, fx, fy, fz, dn, rc);
+    phi[s] = dn / rc;
+}
+
+// Exchange slot of a direction with c_y != 0 (the in-plane neighbours in
+// other rows go through LDS; rows are wavefronts, so c_y = 0 neighbours are
+// lane shuffles).
+__host__ __device__ constexpr int xch_slot(int i) {
+    return i == 3 ? 0 : i == 4 ? 1 : i == 7 ? 2 : i == 8 ? 3 : i == 9 ? 4 : i == 10 ? 5
+         : i == 15 ? 6 : i == 16 ? 7 : i == 17 ? 8 : i == 18 ? 9 : -1;
+}
+constexpr int kXchDirs = 10;
+
+template <typename R, int TX, int TY>
+__host__ __device__ constexpr size_t xch_bytes() {
+    return (size_t)2 * kXchDirs * TX * TY * sizeof(R);
+}
+// One tile of the single pass: columns [x0, x0+TX) x [y0, y0+TY), planes
+// [za, zb); blockDim.x == TX * TY and TX is the wavefront size.  Every thread
+// of the workgroup must call it (it holds barriers).
+template <typename R, typename Src, typename Dst, int TX, int TY, int H>
+__device__ __forceinline__ void single_tile(const Geom& g, const Src& src, const Dst& dst, const Coeffs<R>& c,
+                                            const PhiRing<R, TX, H>& ring, const RecRing<TX>& rr,
+                                            R* __restrict__ xch, int x0, int y0, int za, int zb,
+                                            const R* __restrict__ phi_in, Part2<R>* __restrict__ part_out) {
+    using L = Lattice;
+    constexpr int LX = TX + 2 * H;
+    constexpr int NP = 2 * H + 1;
+    constexpr int NT = TX * TY;
+    constexpr int LY = TY + 2 * H;
+    const int tid = threadIdx.x;
+    const int ty_ = tid / TX, tx_ = tid - (tid / TX) * TX;
+    const int x_ = x0 + tx_, y_ = y0 + ty_;
+    const bool active = x_ < g.nx && y_ < g.ny;
+    const int x1 = min(x0 + TX, g.nx), y1 = min(y0 + TY, g.ny);
+    Src srcr = src;
+    if constexpr (Src::ring) srcr.ring_plane_floats = rr.LY * RecRing<TX>::LX * 8;
+    // own sums of the destination planes cz - 1 (prev), cz (cur)
+    R prev_dn = R(0), prev_rc = R(0), cur_dn = R(0), cur_rc = R(0);
+
+    for (int p = za - H; p < zb + H; ++p) {
+        const int slot = (p - (za - H)) % NP;
+        // ---- phase field of plane p on the tile and its halo
+        {
+            R* dstp = ring.plane(slot);
+            const int zz = halo_coord(p, g.nz, g.wz);
+            for (int q = tid; q < LY * LX; q += NT) {
+                const int ly = q / LX, lx = q - ly * LX;
+                const int xx = halo_coord(x0 - H + lx, g.nx, g.wx);
+                const int yy = halo_coord(y0 - H + ly, g.ny, g.wy);
+                dstp[q] = phi_in[site_of(g, xx, yy, zz)];
+            }
+        }
+        if constexpr (Src::ring) {
+            const int qr = p - H + 1;
+            if (qr >= za - 1 && qr <= zb) load_rec_plane<Src, TX>(g, src, rr, (qr - za + 1) % 3, x0, y0, qr);
+        }
+        __syncthreads();
+        const int cz = p - H;
+        if (cz >= za) {
+            // ---- collide (x, y, cz)
+            R t[Q], d[Q];
+#pragma unroll
+            for (int i = 0; i < Q; ++i) t[i] = d[i] = R(0);
+            if (active) {
+                // the site's coordinates, re-read each plane: kept loop-invariant, the
+                // compiler hoists every stencil address out of the z loop and runs out
+                // of registers
+                int x = x_, y = y_, tx = tx_, ty = ty_;
+                asm volatile("" : "+v"(x), "+v"(y), "+v"(tx), "+v"(ty));
+                const int s0 = (cz - (za - H)) % NP;
+                const int sm = (s0 + NP - 1) % NP, sp = (s0 + 1) % NP;
+                const int s = site_of(g, x, y, cz);
+                if constexpr (Src::ring) {
+                    const f4* const planes[3] = {rr.plane((cz - za) % 3), rr.plane((cz - za + 1) % 3),
+                                                 rr.plane((cz - za + 2) % 3)};
+                    srcr.pull_ring(g, s, x, y, cz, t, d, planes, ty + 1, tx + 1, RecRing<TX>::LX);
+                } else {
+                    src.pull(g, s, x, y, cz, t, d);
+                }
+                const int ly = ty + H, lx = tx + H;
+                R gx, gy, gz;
+                lds_gradient<R, TX, H>(ring, sm, s0, sp, ly, lx, gx, gy, gz);
+                R Fx = c.fx, Fy = c.fy, Fz = c.fz;
+                if (H > 1 && c.nc_range > 0)
+                    ring_near_contact<R, TX, H>(g, ring, s0, x, y, cz, ly, lx, gx, gy, gz, c, Fx, Fy, Fz);
+                SiteTotals<R> tot;
+                collide<R>(t, d, gx, gy, gz, Fx, Fy, Fz, c, &tot);
+                dst.store_as_read(s, t, d, tot);
+                // bounce-backs into this site: its own values, before the in-plane group
+#pragma unroll
+                for (int i = 1; i < Q; ++i) {
+                    int dir;
+                    (void)pull_source(g, i, x, y, cz, s, dir);
+                    if (dir == i) continue;
+                    cur_rc += weight<R>(i) + t[L::opp[i]];
+                    cur_dn += d[L::opp[i]];
+                }
+            }
+            // ---- hand the stored values to the destinations of this plane's
+            // populations: other rows through LDS, the same row by shuffles
+            R sh_t[Q], sh_d[Q];
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                const R a = weight<R>(i) + t[i];
+                if (L::cy[i] != 0) {
+                    xch[(2 * xch_slot(i)) * NT + tid] = a;
+                    xch[(2 * xch_slot(i) + 1) * NT + tid] = d[i];
+                } else if (L::cx[i] > 0) {
+                    sh_t[i] = __shfl_up(a, 1, TX);
+                    sh_d[i] = __shfl_up(d[i], 1, TX);
+                } else if (L::cx[i] < 0) {
+                    sh_t[i] = __shfl_down(a, 1, TX);
+                    sh_d[i] = __shfl_down(d[i], 1, TX);
+                } else {
+                    sh_t[i] = a;
+                    sh_d[i] = d[i];
+                }
+            }
+            __syncthreads();
+            if (active) {
+                int x = x_, y = y_, tx = tx_, ty = ty_;
+                asm volatile("" : "+v"(x), "+v"(y), "+v"(tx), "+v"(ty));
+                // value of direction i from the source (x - cx, y - cy) in plane cz
+                auto from = [&](int i, R& va, R& vd) {
+                    if (L::cy[i] != 0) {
+                        const int at = (ty - L::cy[i]) * TX + tx - L::cx[i];
+                        va = xch[(2 * xch_slot(i)) * NT + at];
+                        vd = xch[(2 * xch_slot(i) + 1) * NT + at];
+                    } else {
+                        va = sh_t[i];
+                        vd = sh_d[i];
+                    }
+                };
+                auto in_tile = [&](int i) {
+                    const int xs = x - L::cx[i], ys = y - L::cy[i];
+                    return xs >= x0 && xs < x1 && ys >= y0 && ys < y1;
+                };
+                // destination cz - 1: sources in plane cz are its last group
+                if (cz - 1 >= za) {
+#pragma unroll
+                    for (int i = 0; i < Q; ++i) {
+                        if (L::cz[i] != -1) continue;
+                        int dir;
+                        (void)pull_source(g, i, x, y, cz - 1, 0, dir);
+                        if (dir != i || !in_tile(i)) continue;
+                        R va, vd;
+                        from(i, va, vd);
+                        prev_rc += va;
+                        prev_dn += vd;
+                    }
+                    part_out[site_of(g, x, y, cz - 1)] = Part2<R>{prev_dn, prev_rc};
+                }
+                // destination cz: in-plane sources
+#pragma unroll
+                for (int i = 0; i < Q; ++i) {
+                    if (L::cz[i] != 0) continue;
+                    int dir;
+                    (void)pull_source(g, i, x, y, cz, 0, dir);
+                    if (dir != i || !in_tile(i)) continue;
+                    R va, vd;
+                    from(i, va, vd);
+                    cur_rc += va;
+                    cur_dn += vd;
+                }
+                // destination cz + 1: sources in plane cz are its first group
+                R next_dn = R(0), next_rc = R(0);
+                if (cz + 1 < zb) {
+#pragma unroll
+                    for (int i = 0; i < Q; ++i) {
+                        if (L::cz[i] != 1) continue;
+                        int dir;
+                        (void)pull_source(g, i, x, y, cz + 1, 0, dir);
+                        if (dir != i || !in_tile(i)) continue;
+                        R va, vd;
+                        from(i, va, vd);
+                        next_rc += va;
+                        next_dn += vd;
+                    }
+                }
+                prev_dn = cur_dn;
+                prev_rc = cur_rc;
+                cur_dn = next_dn;
+                cur_rc = next_rc;
+                // the chunk's last plane has no own sources above it
+                if (cz == zb - 1) part_out[site_of(g, x, y, cz)] = Part2<R>{prev_dn, prev_rc};
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <typename R, typename Src, typename Dst, int TX, int H>
+__global__ __launch_bounds__(TX * kSingleTY) void single_kernel(Geom g, Src src, Dst dst, Coeffs<R> c, FusedShape fs,
+                                                               const R* __restrict__ phi_in,
+                                                               Part2<R>* __restrict__ part_out) {
+    constexpr int TY = kSingleTY;
+    extern __shared__ unsigned char lds_raw[];
+    PhiRing<R, TX, H> ring{reinterpret_cast<R*>(lds_raw), TY + 2 * H};
+    size_t off = (phi_ring_bytes<R, TX, H>(TY) + 15) & ~size_t(15);
+    RecRing<TX> rr{reinterpret_cast<f4*>(lds_raw + off), TY + 2};
+    if constexpr (Src::ring) off += rec_ring_bytes<TX>(TY);
+    R* xch = reinterpret_cast<R*>(lds_raw + off);
+    int x0, y0, za, zb;
+    tile_of_block(fs, TX, g.nz, x0, y0, za, zb);
+    single_tile<R, Src, Dst, TX, TY, H>(g, src, dst, c, ring, rr, xch, x0, y0, za, zb, phi_in, part_out);
+}
+
+}  // namespace lbm
