@@ -121,7 +121,7 @@ struct lb_t {
     void* buf[2];      // post-collision populations, ping-pong
     void* pending;     // raw FP32 state of a 16-bit lattice before its first step
     void* phi;         // phase field of the two-pass step (double for F64, float otherwise)
-    void* part[2];     // own phase sums of the single-pass step, ping-pong
+    void* part[2];     // own phase sums of the one-read step, ping-pong
     int part_cur;      // part[part_cur] belongs to the current state ...
     bool part_valid;   // ... when this is set
     Neu* partial;      // reduction partials

@@ -110,52 +110,60 @@ int zmarch(const LatticeView& v, const Src& src, const Dst& dst, const Coeffs<R>
     return set_error(LB_EINVAL, "near-contact range outside the tile kernels' halo");
 }
 
-// Single pass: the own partial sums of the current state come from the
-// previous single-pass step, or from part_kernel when no such step made it.
-template <typename R, typename Src, typename Dst, int H>
+// One-read step: the own partial sums of the current state come from the
+// previous one-read step, or from part_kernel when no such step made them;
+// assemble_kernel adds the cross-tile terms into phi; the tile kernel
+// collides, streams and gathers the next state's own sums.
+template <typename R, typename Src, typename Dst, int TY, int H>
 int single_h(const LatticeView& v, const Src& src, const Dst& dst, const Coeffs<R>& c, const FusedShape& fs) {
-    const size_t lds = tile_lds(*v.p, TILE_SINGLE, kSingleTY);
-    auto kern = single_kernel<R, Src, Dst, kTX, H>;
+    const size_t lds = tile_lds(*v.p, TILE_SINGLE, TY);
+    auto kern = single_kernel<R, Src, Dst, kTX, TY, H>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return set_error(LB_EDEVICE, (std::string("single_kernel LDS: ") + hipGetErrorString(e)).c_str());
     }
-    hipLaunchKernelGGL(kern, dim3(fs.nblocks), dim3(kTX * kSingleTY), lds, v.stream, v.g, src, dst, c, fs,
+    hipLaunchKernelGGL(kern, dim3(fs.nblocks), dim3(kTX * TY), lds, v.stream, v.g, src, dst, c, fs,
                        (const R*)v.phi, (Part2<R>*)v.part_out);
     return launch_status("single_kernel");
 }
 
-template <typename R, typename Src, typename Dst>
-int single_pass(const LatticeView& v, const Src& src, const Dst& dst, const Coeffs<R>& c, const StepEvents* t) {
-    if (!v.part_in || !v.part_out || !v.phi) return set_error(LB_EINVAL, "single pass without phase buffers");
-    const FusedShape fs = tile_shape(*v.p, TILE_SINGLE);
-    if (fs.TY != kSingleTY) return set_error(LB_EINVAL, "single-pass tile does not fit in LDS");
-    if (t) (void)hipEventRecord(t->ev[0], v.stream);
+template <typename R, typename Src, typename Dst, int TY>
+int single_ty(const LatticeView& v, const Src& src, const Dst& dst, const Coeffs<R>& c, const FusedShape& fs,
+              const StepEvents* t) {
     if (!v.part_valid) {
-        hipLaunchKernelGGL((part_kernel<R, Src, kTX, kSingleTY>), dim3(grid_for(v.g.N)), dim3(kBlock), 0, v.stream,
-                           v.g, src, fs.TZ, (Part2<R>*)v.part_in);
+        hipLaunchKernelGGL((part_kernel<R, Src, kTX, TY>), dim3(grid_for(v.g.N)), dim3(kBlock), 0, v.stream, v.g,
+                           src, fs.TZ, (Part2<R>*)v.part_in);
         int rc = launch_status("part_kernel");
         if (rc) return rc;
     }
-    hipLaunchKernelGGL((assemble_kernel<R, Src, kTX, kSingleTY>), dim3(grid_for(v.g.N)), dim3(kBlock), 0, v.stream,
-                       v.g, src, fs.TZ, (const Part2<R>*)v.part_in, (R*)v.phi);
-    {
-        int rc = launch_status("assemble_kernel");
-        if (rc) return rc;
-    }
+    hipLaunchKernelGGL((assemble_kernel<R, Src, kTX, TY>), dim3(grid_for(v.g.N)), dim3(kBlock), 0, v.stream, v.g,
+                       src, fs.TZ, (const Part2<R>*)v.part_in, (R*)v.phi);
+    int rc = launch_status("assemble_kernel");
+    if (rc) return rc;
     if (t) (void)hipEventRecord(t->ev[1], v.stream);
-    int rc;
     switch (tile_halo(*v.p)) {
-        case 1: rc = single_h<R, Src, Dst, 1>(v, src, dst, c, fs); break;
-        case 2: rc = single_h<R, Src, Dst, 2>(v, src, dst, c, fs); break;
-        case 3: rc = single_h<R, Src, Dst, 3>(v, src, dst, c, fs); break;
-        case 4: rc = single_h<R, Src, Dst, 4>(v, src, dst, c, fs); break;
-        case 5: rc = single_h<R, Src, Dst, 5>(v, src, dst, c, fs); break;
-        default: return set_error(LB_EINVAL, "near-contact range outside the tile kernels' halo");
+        case 1: return single_h<R, Src, Dst, TY, 1>(v, src, dst, c, fs);
+        case 2: return single_h<R, Src, Dst, TY, 2>(v, src, dst, c, fs);
+        case 3: return single_h<R, Src, Dst, TY, 3>(v, src, dst, c, fs);
+        case 4: return single_h<R, Src, Dst, TY, 4>(v, src, dst, c, fs);
+        case 5: return single_h<R, Src, Dst, TY, 5>(v, src, dst, c, fs);
     }
+    return set_error(LB_EINVAL, "near-contact range outside the tile kernels' halo");
+}
+
+template <typename R, typename Src, typename Dst>
+int single_pass(const LatticeView& v, const Src& src, const Dst& dst, const Coeffs<R>& c, const StepEvents* t) {
+    if (!v.part_in || !v.part_out || !v.phi) return set_error(LB_EINVAL, "one-read step without its phase buffers");
+    const FusedShape fs = tile_shape(*v.p, TILE_SINGLE);
+    if (t) (void)hipEventRecord(t->ev[0], v.stream);
+    int rc;
+    if (fs.TY == kSingleTY) rc = single_ty<R, Src, Dst, kSingleTY>(v, src, dst, c, fs, t);
+    else if (fs.TY == kSingleTYSmall) rc = single_ty<R, Src, Dst, kSingleTYSmall>(v, src, dst, c, fs, t);
+    else return set_error(LB_EINVAL, "one-read tile does not fit in LDS");
+    if (rc) return rc;
     if (t) (void)hipEventRecord(t->ev[2], v.stream);
-    return rc;
+    return LB_OK;
 }
 
 // Phase pass: raw storage pulls site by site; 16-bit moment-split storage
@@ -229,7 +237,11 @@ size_t tile_lds(const lb_params& p, int kind, int TY) {
 // Tile rows: preferred per kind and storage (measured on MI355X), else the
 // largest that keeps the LDS rings within the per-workgroup budget.
 int tile_rows(const lb_params& p, int kind) {
-    if (kind == TILE_SINGLE) return tile_lds(p, kind, kSingleTY) <= (size_t)device_lds_bytes() ? kSingleTY : 0;
+    if (kind == TILE_SINGLE) {
+        for (int ty : {kSingleTY, kSingleTYSmall})
+            if (tile_lds(p, kind, ty) <= (size_t)device_lds_bytes()) return ty;
+        return 0;
+    }
     const char* env = kind == TILE_PHASE ? "LB_PHASE_TY" : "LB_COLLIDE_TY";
     int want = env_int(env, 0);
     if (want <= 0) {

@@ -30,8 +30,10 @@ struct Part2 {
     R dn, rc;
 };
 
-// Rows of the single-pass tile (one site per thread and plane).
+// Rows of the one-read tile (one site per thread and plane): 8, or 4 when
+// the LDS of 8 rows exceeds the workgroup's budget (FP64 with a wide halo).
 constexpr int kSingleTY = 8;
+constexpr int kSingleTYSmall = 4;
 
 // Own box of a site: its tile column [x0, x1) x [y0, y1) and z chunk [z0, z1).
 struct OwnBox {
@@ -334,11 +336,10 @@ __device__ __forceinline__ void single_tile(const Geom& g, const Src& src, const
     }
 }
 
-template <typename R, typename Src, typename Dst, int TX, int H>
-__global__ __launch_bounds__(TX * kSingleTY) void single_kernel(Geom g, Src src, Dst dst, Coeffs<R> c, FusedShape fs,
-                                                               const R* __restrict__ phi_in,
-                                                               Part2<R>* __restrict__ part_out) {
-    constexpr int TY = kSingleTY;
+template <typename R, typename Src, typename Dst, int TX, int TY, int H>
+__global__ __launch_bounds__(TX * TY) void single_kernel(Geom g, Src src, Dst dst, Coeffs<R> c, FusedShape fs,
+                                                        const R* __restrict__ phi_in,
+                                                        Part2<R>* __restrict__ part_out) {
     extern __shared__ unsigned char lds_raw[];
     PhiRing<R, TX, H> ring{reinterpret_cast<R*>(lds_raw), TY + 2 * H};
     size_t off = (phi_ring_bytes<R, TX, H>(TY) + 15) & ~size_t(15);
