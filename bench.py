@@ -303,7 +303,8 @@ def main():
     head = results.get("f32") or next(iter(results.values()))
     head_name = "f32" if "f32" in results else next(iter(results))
     st = codes[head_name]
-    # dominant kernel: the collide-and-stream (or fused) pass
+    # dominant kernel: the collide-and-stream pass (pass_ms[1]; pass_ms[0] is the
+    # phase pass of two-pass steps or the phase assembly of one-read steps)
     dom_ms = head["pass_ms"][1]
     achieved = ALGO_BYTES[st] * w.sites / (dom_ms * 1e-3) / 1e9
     traffic = measured_traffic("collide_" + head_name, args.n)
@@ -312,7 +313,8 @@ def main():
             "traffic": None if traffic is None else round(traffic / 1e9, 3),
             "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE)",
             "kernel": ("collide pass (z-marching fused_kernel, phase field from the phase pass)"
-                       if head["kernel"] == 1 else "single-pass fused_kernel"),
+                       if head["kernel"] == 1 else
+                       "one-read collide tile (single_kernel; phase field assembled by assemble_kernel)"),
             "algo_bytes_per_site": ALGO_BYTES[st], "sites_per_launch": w.sites,
             "kernel_ms": round(dom_ms, 4)}
 
@@ -347,7 +349,7 @@ def main():
         "config": {"workload": "periodic emulsion %d^3, phi_v 0.30, R U[6,12], tau 0.8, A 0.005, "
                                "beta 0.7, near-contact 0.02 over 2 sites" % args.n,
                    "sites": w.sites, "storage": head_name,
-                   "kernel": "two-pass" if head["kernel"] == 1 else "fused",
+                   "kernel": "two-pass" if head["kernel"] == 1 else "one-read",
                    "parallelism": "single GPU"},
         "hbm_gbs_algorithmic": round(head["algo_gbs"], 1),
         "hbm_frac_algorithmic": round(head["algo_gbs"] / HBM_PEAK_GBS, 4),
