@@ -332,7 +332,10 @@ __device__ __forceinline__ void single_tile(const Geom& g, const Src& src, const
                 if (cz == zb - 1) part_out[site_of(g, x, y, cz)] = Part2<R>{prev_dn, prev_rc};
             }
         }
-        __syncthreads();
+        // no barrier here: the next staging overwrites ring and record slots
+        // that only this plane's collide read, and every thread passed the
+        // barrier after that collide before it gathers; the exchange buffer is
+        // next written after the next staging's barrier
     }
 }
 
