@@ -238,8 +238,12 @@ size_t tile_lds(const lb_params& p, int kind, int TY) {
 // largest that keeps the LDS rings within the per-workgroup budget.
 int tile_rows(const lb_params& p, int kind) {
     if (kind == TILE_SINGLE) {
-        for (int ty : {kSingleTY, kSingleTYSmall})
-            if (tile_lds(p, kind, ty) <= (size_t)device_lds_bytes()) return ty;
+        // 8 rows for raw storage; 16-bit storage takes 4 (its record ring makes
+        // 8 rows a one-workgroup-per-CU tile)
+        const int want = env_int("LB_SINGLE_TY", split_storage(p) ? kSingleTYSmall : kSingleTY);
+        for (int ty : {want, kSingleTYSmall})
+            if ((ty == kSingleTY || ty == kSingleTYSmall) && tile_lds(p, kind, ty) <= (size_t)device_lds_bytes())
+                return ty;
         return 0;
     }
     const char* env = kind == TILE_PHASE ? "LB_PHASE_TY" : "LB_COLLIDE_TY";

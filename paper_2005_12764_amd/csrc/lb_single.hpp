@@ -91,6 +91,22 @@ __global__ __launch_bounds__(256) void part_kernel(Geom g, Src src, int TZ, Part
     part[s] = Part2<R>{dn, rc};
 }
 
+// Walls next to a site: direction i arriving there is a bounce-back exactly
+// when its upstream site lies beyond one of them (the test pull_source makes,
+// without computing the upstream index).
+struct WallFlags {
+    bool xlo, xhi, ylo, yhi, zlo, zhi;
+};
+__device__ __forceinline__ WallFlags wall_flags(const Geom& g, int x, int y, int z) {
+    return WallFlags{g.wx && x == 0, g.wx && x == g.nx - 1, g.wy && y == 0,
+                     g.wy && y == g.ny - 1, g.wz && z == 0, g.wz && z == g.nz - 1};
+}
+__device__ __forceinline__ bool reflected(int i, const WallFlags& w) {
+    using L = Lattice;
+    return (L::cx[i] > 0 && w.xlo) || (L::cx[i] < 0 && w.xhi) || (L::cy[i] > 0 && w.ylo) ||
+           (L::cy[i] < 0 && w.yhi) || (L::cz[i] > 0 && w.zlo) || (L::cz[i] < 0 && w.zhi);
+}
+
 // Faces of a site's own box along one axis: lo = first coordinate of its
 // tile (sources at v - 1 lie outside), hi = last (sources at v + 1 outside).
 struct Faces {
@@ -234,11 +250,10 @@ __device__ __forceinline__ void single_tile(const Geom& g, const Src& src, const
                 collide<R>(t, d, gx, gy, gz, Fx, Fy, Fz, c, &tot);
                 dst.store_as_read(s, t, d, tot);
                 // bounce-backs into this site: its own values, before the in-plane group
+                const WallFlags wf = wall_flags(g, x, y, cz);
 #pragma unroll
                 for (int i = 1; i < Q; ++i) {
-                    int dir;
-                    (void)pull_source(g, i, x, y, cz, s, dir);
-                    if (dir == i) continue;
+                    if (!reflected(i, wf)) continue;
                     cur_rc += weight<R>(i) + t[L::opp[i]];
                     cur_dn += d[L::opp[i]];
                 }
@@ -284,12 +299,11 @@ __device__ __forceinline__ void single_tile(const Geom& g, const Src& src, const
                 };
                 // destination cz - 1: sources in plane cz are its last group
                 if (cz - 1 >= za) {
+                    const WallFlags wm = wall_flags(g, x, y, cz - 1);
 #pragma unroll
                     for (int i = 0; i < Q; ++i) {
                         if (L::cz[i] != -1) continue;
-                        int dir;
-                        (void)pull_source(g, i, x, y, cz - 1, 0, dir);
-                        if (dir != i || !in_tile(i)) continue;
+                        if (reflected(i, wm) || !in_tile(i)) continue;
                         R va, vd;
                         from(i, va, vd);
                         prev_rc += va;
@@ -298,12 +312,11 @@ __device__ __forceinline__ void single_tile(const Geom& g, const Src& src, const
                     part_out[site_of(g, x, y, cz - 1)] = Part2<R>{prev_dn, prev_rc};
                 }
                 // destination cz: in-plane sources
+                const WallFlags w0 = wall_flags(g, x, y, cz);
 #pragma unroll
                 for (int i = 0; i < Q; ++i) {
                     if (L::cz[i] != 0) continue;
-                    int dir;
-                    (void)pull_source(g, i, x, y, cz, 0, dir);
-                    if (dir != i || !in_tile(i)) continue;
+                    if (reflected(i, w0) || !in_tile(i)) continue;
                     R va, vd;
                     from(i, va, vd);
                     cur_rc += va;
@@ -312,12 +325,11 @@ __device__ __forceinline__ void single_tile(const Geom& g, const Src& src, const
                 // destination cz + 1: sources in plane cz are its first group
                 R next_dn = R(0), next_rc = R(0);
                 if (cz + 1 < zb) {
+                    const WallFlags wp = wall_flags(g, x, y, cz + 1);
 #pragma unroll
                     for (int i = 0; i < Q; ++i) {
                         if (L::cz[i] != 1) continue;
-                        int dir;
-                        (void)pull_source(g, i, x, y, cz + 1, 0, dir);
-                        if (dir != i || !in_tile(i)) continue;
+                        if (reflected(i, wp) || !in_tile(i)) continue;
                         R va, vd;
                         from(i, va, vd);
                         next_rc += va;
