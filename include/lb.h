@@ -64,9 +64,13 @@ extern "C" {
 #define LB_STORE_BF16 3 /* as LB_STORE_F16 with bf16 deviations (no scale) */
 
 /* Kernel selection for lb_step. */
-#define LB_KERNEL_AUTO 0    /* fused when the lattice allows it, else two-pass */
+#define LB_KERNEL_AUTO 0    /* one-read for FP64/FP32 without moving walls, else two-pass */
 #define LB_KERNEL_TWOPASS 1 /* phase-field pass, then collide-and-stream pass */
-#define LB_KERNEL_FUSED 2   /* single pass: z-marching tiles, phase field in LDS */
+#define LB_KERNEL_FUSED 2   /* one-read step: the collide-and-stream tiles also gather the
+                               next phase field's sums, a light pass adds the terms
+                               that cross tiles; every population is read once per
+                               step.  Lattices with moving walls step with two passes
+                               after their first step. */
 
 /* Element type of caller fields. */
 #define LB_DTYPE_F64 0
@@ -132,8 +136,9 @@ int lb_step(lb_t* h, int32_t n);
 
 /* As lb_step, timing every pass with HIP events on the handle's stream;
  * blocks until the n steps are done.  kernel_ms (host, 3 values) receives the
- * mean milliseconds per step of: [0] the phase-field pass (0 for the fused
- * kernel), [1] the collide-and-stream (or fused) pass, [2] the whole step. */
+ * mean milliseconds per step of: [0] the phase-field pass (two-pass) or the
+ * phase-field assembly (one-read), [1] the collide-and-stream pass, [2] the
+ * whole step. */
 int lb_step_timed(lb_t* h, int32_t n, double kernel_ms[3]);
 
 /* Moments of the current state (Sec. 2, eq:eq2): rho_r, rho_b (N each) and the

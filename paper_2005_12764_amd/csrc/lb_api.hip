@@ -334,8 +334,8 @@ int lb_init_droplets(lb_t* h, const double* centres, const double* radii, int32_
 }
 
 // One step of lattice h (events t may be null); `used` receives the kernel
-// that ran.  Lattices with moving walls step with two passes (the single
-// pass carries no wall terms).
+// that ran.  Lattices with moving walls step with two passes (the one-read
+// step carries no wall terms).
 static int advance(lb_t* h, const StepEvents* t, int* used) {
     LatticeView v = view_of(h);
     const int kernel = (h->kernel == LB_KERNEL_FUSED && v.g.moving) ? LB_KERNEL_TWOPASS : h->kernel;
@@ -388,8 +388,9 @@ int lb_step_timed(lb_t* h, int32_t n, double kernel_ms[3]) {
     double a = 0, b = 0, c = 0;
     if (!rc) {
         for (int32_t k = 0; k < n; ++k) {
-            // two-pass: [0] phase pass, [1] collide pass; single pass: [0] the
-            // phase sums of a state no single pass produced, [1] the pass
+            // two-pass: [0] phase pass, [1] collide pass; one-read: [0] the phase
+            // assembly (and the own sums of a state no one-read step made), [1]
+            // the collide tile
             float t01 = 0, t12 = 0, t02 = 0;
             (void)hipEventElapsedTime(&t01, ev[k].ev[0], ev[k].ev[1]);
             (void)hipEventElapsedTime(&t12, ev[k].ev[1], ev[k].ev[2]);

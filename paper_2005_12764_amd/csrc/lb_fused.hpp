@@ -1,21 +1,15 @@
-// lb_fused.hpp -- z-marching tile kernels.
+// lb_fused.hpp -- z-marching tile kernels of the two-pass step.
 //
 // A workgroup owns a tile of TX x TY columns and marches it through a chunk of
 // z-planes, keeping the phase field phi in an LDS ring of 2H+1 planes (tile
 // plus a halo of H = K + 1 sites, K = near-contact range).  The plane H behind
 // the newest one then has phi on every site its colour gradient and the
-// gradients along its near-contact probes can reach, and is collided.
-//
-// Two uses:
-//  - collide pass of the two-pass step: phi comes from the phase pass's array,
-//    so each site's populations are read once; for 16-bit moment-split
-//    storage the per-site FP32 records of planes z-1..z+1 (tile plus one site)
-//    are staged in a second LDS ring so that the 19 source records of a pull
-//    come from LDS;
-//  - single pass: phi of the tile and its halo is computed from pulled
-//    populations, and interior sites pull again to collide.  Measured slower
-//    than two passes on MI355X: the second pull comes H planes later, when the
-//    chip-wide working set (hundreds of MB) no longer fits the caches.
+// gradients along its near-contact probes can reach, and is collided.  phi
+// comes from the phase pass's array, so each site's populations are read once
+// by the collide pass; for 16-bit moment-split storage the per-site FP32
+// records of planes z-1..z+1 (tile plus one site) are staged in a second LDS
+// ring so that the 19 source records of a pull come from LDS.  The phase pass
+// of 16-bit storage marches the same tiles with the record ring only.
 #pragma once
 #include "lb_kernels.hpp"
 
@@ -152,11 +146,10 @@ __device__ __forceinline__ void ring_near_contact(const Geom& g, const PhiRing<R
     Fz += ah * gz;
 }
 
-// One tile: columns [x0, x0+TX) x [y0, y0+TY), planes [za, zb).  Every thread
-// of the workgroup must call it (it holds barriers).
-//   phi_in == nullptr: single pass (phi from pulled populations);
-//   otherwise collide pass with phi from the phase pass, and, for storage
-//   with per-site records, the records of planes z-1..z+1 in `rr`.
+// One tile of the collide pass: columns [x0, x0+TX) x [y0, y0+TY), planes
+// [za, zb), phi from the phase pass and, for storage with per-site records,
+// the records of planes z-1..z+1 in `rr`.  Every thread of the workgroup must
+// call it (it holds barriers).
 template <typename R, typename Src, typename Dst, int TX, int H>
 __device__ __forceinline__ void fused_tile(const Geom& g, const Src& src, const Dst& dst, const Coeffs<R>& c,
                                            const PhiRing<R, TX, H>& ring, int TY, int x0, int y0, int za,
@@ -166,7 +159,6 @@ __device__ __forceinline__ void fused_tile(const Geom& g, const Src& src, const 
     const int LY = ring.LY;
     const int tid = threadIdx.x;
     const int nt = blockDim.x;
-    const bool use_ring = Src::ring && phi_in != nullptr;
     Src srcr = src;
     if constexpr (Src::ring) srcr.ring_plane_floats = rr.LY * RecRing<TX>::LX * 8;
     for (int p = za - H; p < zb + H; ++p) {
@@ -179,20 +171,13 @@ __device__ __forceinline__ void fused_tile(const Geom& g, const Src& src, const 
                 const int ly = q / LX, lx = q - ly * LX;
                 const int xx = halo_coord(x0 - H + lx, g.nx, g.wx);
                 const int yy = halo_coord(y0 - H + ly, g.ny, g.wy);
-                const int s = site_of(g, xx, yy, zz);
-                if (phi_in) {
-                    dstp[q] = phi_in[s];
-                    continue;
-                }
-                R t[Q], d[Q];
-                src.pull(g, s, xx, yy, zz, t, d);
-                dstp[q] = phase_of(t, d);
+                dstp[q] = phi_in[site_of(g, xx, yy, zz)];
             }
         }
         if constexpr (Src::ring) {
             // records of plane cz + 1 (planes cz - 1 and cz came in earlier)
             const int qr = p - H + 1;
-            if (use_ring && qr >= za - 1 && qr <= zb) load_rec_plane<Src, TX>(g, src, rr, (qr - za + 1) % 3, x0, y0, qr);
+            if (qr >= za - 1 && qr <= zb) load_rec_plane<Src, TX>(g, src, rr, (qr - za + 1) % 3, x0, y0, qr);
         }
         __syncthreads();
         // ---- collide plane cz = p - H: its phi neighbourhood is complete
@@ -207,13 +192,9 @@ __device__ __forceinline__ void fused_tile(const Geom& g, const Src& src, const 
                 const int s = site_of(g, x, y, cz);
                 R t[Q], d[Q];
                 if constexpr (Src::ring) {
-                    if (use_ring) {
-                        const f4* const planes[3] = {rr.plane((cz - za) % 3), rr.plane((cz - za + 1) % 3),
-                                                     rr.plane((cz - za + 2) % 3)};
-                        srcr.pull_ring(g, s, x, y, cz, t, d, planes, ty + 1, tx + 1, RecRing<TX>::LX);
-                    } else {
-                        src.pull(g, s, x, y, cz, t, d);
-                    }
+                    const f4* const planes[3] = {rr.plane((cz - za) % 3), rr.plane((cz - za + 1) % 3),
+                                                 rr.plane((cz - za + 2) % 3)};
+                    srcr.pull_ring(g, s, x, y, cz, t, d, planes, ty + 1, tx + 1, RecRing<TX>::LX);
                 } else {
                     src.pull(g, s, x, y, cz, t, d);
                 }

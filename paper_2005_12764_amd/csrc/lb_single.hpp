@@ -62,7 +62,7 @@ __device__ __forceinline__ int group_of(int i, bool reflected) {
     return reflected ? 1 : (Lattice::cz[i] > 0 ? 0 : (Lattice::cz[i] == 0 ? 2 : 3));
 }
 
-// Own partial sums of the current state, for a state that no single-pass
+// Own partial sums of the current state, for a state that no one-read
 // step produced (initial, imported, or left by a two-pass step).
 template <typename R, typename Src, int TX, int TY>
 __global__ __launch_bounds__(256) void part_kernel(Geom g, Src src, int TZ, Part2<R>* __restrict__ part) {
@@ -177,7 +177,7 @@ template <typename R, int TX, int TY>
 __host__ __device__ constexpr size_t xch_bytes() {
     return (size_t)2 * kXchDirs * TX * TY * sizeof(R);
 }
-// One tile of the single pass: columns [x0, x0+TX) x [y0, y0+TY), planes
+// One tile of the one-read step: columns [x0, x0+TX) x [y0, y0+TY), planes
 // [za, zb); blockDim.x == TX * TY and TX is the wavefront size.  Every thread
 // of the workgroup must call it (it holds barriers).
 template <typename R, typename Src, typename Dst, int TX, int TY, int H>
