@@ -223,7 +223,7 @@ def config_c4(args, stream):
             "steps": marks[-1], "results": res}
 
 
-def cpu_baseline(w, steps):
+def cpu_baseline(w, steps, steps_1t):
     from oracle import oracle as O
     from tests.helpers import oracle_params
 
@@ -232,10 +232,22 @@ def cpu_baseline(w, steps):
     t0 = time.perf_counter()
     O.step(prm, f, steps)
     dt = time.perf_counter() - t0
-    return dict(value=w.sites * steps / dt / 1e6, unit="MLUPS", cores=O.threads(), kind="oracle",
-                sample="%d step(s) of the full %s lattice (%d sites), FP64, OpenMP over sites"
-                       % (steps, "x".join(str(s) for s in w.shape[::-1]), w.sites),
-                seconds=dt)
+    cores = O.threads()
+    out = dict(value=w.sites * steps / dt / 1e6, unit="MLUPS", cores=cores, kind="oracle",
+               sample="%d step(s) of the full %s lattice (%d sites), FP64, OpenMP over sites"
+                      % (steps, "x".join(str(s) for s in w.shape[::-1]), w.sites),
+               seconds=dt)
+    if steps_1t > 0:
+        # the same oracle on one thread (a per-core figure)
+        O.set_threads(1)
+        try:
+            t0 = time.perf_counter()
+            O.step(prm, f, steps_1t)
+            dt1 = time.perf_counter() - t0
+        finally:
+            O.set_threads(cores)
+        out.update(value_1thread=w.sites * steps_1t / dt1 / 1e6, steps_1thread=steps_1t, seconds_1thread=dt1)
+    return out
 
 
 def main():
@@ -247,6 +259,7 @@ def main():
     ap.add_argument("--variants", default="f32,f16,bf16")
     ap.add_argument("--kernel", type=int, default=0, help="0 auto, 1 two-pass, 2 fused")
     ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-steps-1t", type=int, default=1, help="oracle steps on one thread (0 = skip)")
     ap.add_argument("--serve-jobs", type=int, default=200, help="jobs of the serving leg (0 = skip)")
     ap.add_argument("--serve-rate", type=float, default=40.0)
     ap.add_argument("--serve-steps", type=int, default=500)
@@ -330,8 +343,10 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(w, args.cpu_steps)
+        cpu = cpu_baseline(w, args.cpu_steps, args.cpu_steps_1t)
         log("cpu oracle: %.2f MLUPS on %d threads (%.1fs)" % (cpu["value"], cpu["cores"], cpu["seconds"]))
+        if "value_1thread" in cpu:
+            log("cpu oracle: %.3f MLUPS on 1 thread (%.1fs)" % (cpu["value_1thread"], cpu["seconds_1thread"]))
 
     out = {
         "metric": "MLUPS and HBM GB/s (% of peak), FP16-store vs FP32; p50/p99 sweep-job latency",

@@ -192,7 +192,8 @@ int64_t lb_footprint_bytes(const lb_params* p) {
     size_t b = 2 * pop_bytes(p->storage, N) + N * real;
     // phase sums of the one-read step (raw storage unless two passes are asked
     // for; an upper bound for lattices the automatic choice steps otherwise)
-    if (p->storage <= LB_STORE_F32 && p->kernel != LB_KERNEL_TWOPASS) b += 2 * 2 * N * real;
+    if (p->storage <= LB_STORE_F32 && p->kernel != LB_KERNEL_TWOPASS)
+        b += 2 * 2 * part_entries<kTX>(p->nx, p->ny, p->nz) * real;
     return (int64_t)b;
 }
 
@@ -229,7 +230,8 @@ int lb_create(const lb_params* params, void* hip_stream, lb_t** out) {
         return rc;
     }
     if (h->kernel == LB_KERNEL_FUSED) {
-        const size_t pbytes = 2 * N * (h->p.storage == LB_STORE_F64 ? 8 : 4);
+        const size_t pbytes =
+            2 * part_entries<kTX>(h->p.nx, h->p.ny, h->p.nz) * (h->p.storage == LB_STORE_F64 ? 8 : 4);
         if ((rc = check_hip(hipMalloc(&h->part[0], pbytes), "hipMalloc phase sums")) ||
             (rc = check_hip(hipMalloc(&h->part[1], pbytes), "hipMalloc phase sums"))) {
             release(h);

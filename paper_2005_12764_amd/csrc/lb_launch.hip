@@ -229,8 +229,10 @@ size_t tile_lds(const lb_params& p, int kind, int TY) {
     switch (kind) {
         case TILE_PHASE: return rec;
         case TILE_COLLIDE: return ((phi + 15) & ~size_t(15)) + (split ? rec : 0);
-        default:  // TILE_SINGLE: phi ring, record ring, exchange of the c_y != 0 directions
-            return ((phi + 15) & ~size_t(15)) + (split ? rec : 0) + (size_t)2 * kXchDirs * kTX * TY * real_size(p);
+        default:  // TILE_SINGLE: phi ring, record ring, exchange of the c_y != 0 directions,
+                  // running x-face sums of the edge lanes
+            return ((phi + 15) & ~size_t(15)) + (split ? rec : 0) + (size_t)2 * kXchDirs * kTX * TY * real_size(p) +
+                   (size_t)2 * 3 * TY * 2 * real_size(p);
     }
 }
 

@@ -12,13 +12,22 @@
 // population is read from HBM once per step (plus the few foreign ones),
 // instead of once by a phase pass and again by the collide pass.
 //
+// The foreign terms that enter a site through an x face of its box all come
+// from the one neighbouring tile column (a source that is also outside the
+// y or z range of the box belongs to that face instead), so the tile holding
+// those sources sums them per destination and stores the pair in a compact
+// array after the own sums; the assembly reads one pair per x-face site
+// instead of ten scattered values (rows are contiguous in x, so the y and z
+// faces pull whole rows and keep the direct reads).
+//
 // Summation order is fixed, so results are reproducible: the own terms of a
 // site in four groups -- sources in plane z-1, bounce-backs from the site
 // itself, in-plane sources, sources in plane z+1 -- each in ascending
-// direction; then the foreign terms face by face (z, y, x), each in
-// ascending direction.  D and Rc are summed term by term alike,
-// so a pure component (d_i = +-(w_i + t_i)) gives phi = +-1 exactly, as in
-// the collision.
+// direction; then the foreign terms of the z and the y faces, each in
+// ascending direction; then the x-face sums (lo face, then hi face), each
+// summed from zero in the group order of the own terms.  D and Rc are summed
+// term by term alike, so a pure component (d_i = +-(w_i + t_i)) gives
+// phi = +-1 exactly, as in the collision.
 #pragma once
 #include "lb_fused.hpp"
 
@@ -29,6 +38,26 @@ template <typename R>
 struct Part2 {
     R dn, rc;
 };
+
+// Entries of a phase-sum buffer: the N own sums, then the x-face sums of
+// every tile column (2 faces x ny x nz each).
+template <int TX>
+__host__ __device__ constexpr size_t part_entries(int nx, int ny, int nz) {
+    return (size_t)nx * ny * nz + (size_t)2 * ((nx + TX - 1) / TX) * ny * nz;
+}
+
+// x-face sum of the site (x, y, z) on the lo (side 0, x = bx * TX) or hi
+// (side 1) x face of tile column bx, in the compact array after the own sums.
+__device__ __forceinline__ size_t xface_at(const Geom& g, int bx, int side, int y, int z) {
+    return ((size_t)(bx * 2 + side) * g.nz + z) * g.ny + y;
+}
+
+// Direction with velocity (cx, cy, cz).
+__host__ __device__ constexpr int dir_of(int cx, int cy, int cz) {
+    for (int i = 0; i < Q; ++i)
+        if (Lattice::cx[i] == cx && Lattice::cy[i] == cy && Lattice::cz[i] == cz) return i;
+    return -1;
+}
 
 // Rows of the one-read tile (one site per thread and plane): 8, or 4 when
 // the LDS of 8 rows exceeds the workgroup's budget (FP64 with a wide halo).
@@ -62,8 +91,36 @@ __device__ __forceinline__ int group_of(int i, bool reflected) {
     return reflected ? 1 : (Lattice::cz[i] > 0 ? 0 : (Lattice::cz[i] == 0 ? 2 : 3));
 }
 
-// Own partial sums of the current state, for a state that no one-read
-// step produced (initial, imported, or left by a two-pass step).
+// Terms entering the site (x, y, z) with c_x = SX through its x face whose
+// source lies within the y and z range of the site's box b, summed from zero
+// in the group order of the own terms (sources in plane z-1, in-plane
+// sources, sources in plane z+1), each group in ascending direction.
+template <typename R, int SX, typename Src>
+__device__ __forceinline__ Part2<R> xface_sum(const Geom& g, const Src& src, const OwnBox& b, int s, int x, int y,
+                                             int z) {
+    using L = Lattice;
+    R dn = R(0), rc = R(0);
+#pragma unroll
+    for (int grp = 0; grp < 4; ++grp) {
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            if (L::cx[i] != SX || group_of(i, false) != grp) continue;
+            const int ys = y - L::cy[i], zs = z - L::cz[i];
+            if (ys < b.y0 || ys >= b.y1 || zs < b.z0 || zs >= b.z1) continue;
+            int dir;
+            const int sr = pull_source(g, i, x, y, z, s, dir);
+            if (dir != i) continue;
+            R t, d;
+            src.template pull_one<R>(i, sr, dir, t, d);
+            rc += weight<R>(i) + t;
+            dn += d;
+        }
+    }
+    return Part2<R>{dn, rc};
+}
+
+// Own partial sums and x-face sums of the current state, for a state that
+// no one-read step produced (initial, imported, or left by a two-pass step).
 template <typename R, typename Src, int TX, int TY>
 __global__ __launch_bounds__(256) void part_kernel(Geom g, Src src, int TZ, Part2<R>* __restrict__ part) {
     using L = Lattice;
@@ -89,6 +146,12 @@ __global__ __launch_bounds__(256) void part_kernel(Geom g, Src src, int TZ, Part
         }
     }
     part[s] = Part2<R>{dn, rc};
+    // x-face sums of this site (beyond an x wall every term is a bounce-back)
+    Part2<R>* xf = part + g.N;
+    const bool lo = x % TX == 0 && !(g.wx && x == 0);
+    const bool hi = (x % TX == TX - 1 || x == g.nx - 1) && !(g.wx && x == g.nx - 1);
+    if (lo) xf[xface_at(g, x / TX, 0, y, z)] = xface_sum<R, 1>(g, src, b, s, x, y, z);
+    if (hi) xf[xface_at(g, x / TX, 1, y, z)] = xface_sum<R, -1>(g, src, b, s, x, y, z);
 }
 
 // Walls next to a site: direction i arriving there is a bounce-back exactly
@@ -124,17 +187,16 @@ __device__ __forceinline__ Faces faces_z(int v, int z0, int z1) { return Faces{v
 __device__ __forceinline__ bool leaves(int c, const Faces& f) { return (c > 0 && f.lo) || (c < 0 && f.hi); }
 
 // Foreign terms of site s = (x, y, z) whose source lies outside the box
-// through the faces of `axis` (0 = x, 1 = y, 2 = z) and not through those of
-// an axis summed before it (z, then y, then x); bounce-backs are own terms.
+// through the faces of `axis` (1 = y, 2 = z) and not through those of an
+// axis summed before it (z, then y); bounce-backs are own terms.
 template <typename R, typename Src, int AXIS>
 __device__ __forceinline__ void foreign_terms(const Geom& g, const Src& src, int s, int x, int y, int z,
-                                              const Faces& fx, const Faces& fy, const Faces& fz, R& dn,
-                                              R& rc) {
+                                              const Faces& fy, const Faces& fz, R& dn, R& rc) {
     using L = Lattice;
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
-        const bool oz = leaves(L::cz[i], fz), oy = leaves(L::cy[i], fy), ox = leaves(L::cx[i], fx);
-        const bool mine = AXIS == 2 ? oz : (AXIS == 1 ? (oy && !oz) : (ox && !oy && !oz));
+        const bool oz = leaves(L::cz[i], fz), oy = leaves(L::cy[i], fy);
+        const bool mine = AXIS == 2 ? oz : (oy && !oz);
         if (!mine) continue;
         int dir;
         const int sr = pull_source(g, i, x, y, z, s, dir);
@@ -146,7 +208,8 @@ __device__ __forceinline__ void foreign_terms(const Geom& g, const Src& src, int
     }
 }
 
-// phi of every site from the own partial sums and the foreign terms.
+// phi of every site from the own partial sums, the foreign terms of the z
+// and y faces and the x-face sums.
 template <typename R, typename Src, int TX, int TY>
 __global__ __launch_bounds__(256) void assemble_kernel(Geom g, Src src, int TZ, const Part2<R>* __restrict__ part,
                                                        R* __restrict__ phi) {
@@ -158,9 +221,19 @@ __global__ __launch_bounds__(256) void assemble_kernel(Geom g, Src src, int TZ, 
     R dn = P.dn, rc = P.rc;
     const int z0 = z - z % TZ;
     const Faces fx = faces_of<TX>(x, g.nx), fy = faces_of<TY>(y, g.ny), fz = faces_z(z, z0, min(z0 + TZ, g.nz));
-    if (fz.lo || fz.hi) foreign_terms<R, Src, 2>(g, src, s, x, y, z, fx, fy, fz, dn, rc);
-    if (fy.lo || fy.hi) foreign_terms<R, Src, 1>(g, src, s, x, y, z, fx, fy, fz, dn, rc);
-    if (fx.lo || fx.hi) foreign_terms<R, Src, 0>(g, src, s, x, y, z, fx, fy, fz, dn, rc);
+    if (fz.lo || fz.hi) foreign_terms<R, Src, 2>(g, src, s, x, y, z, fy, fz, dn, rc);
+    if (fy.lo || fy.hi) foreign_terms<R, Src, 1>(g, src, s, x, y, z, fy, fz, dn, rc);
+    const Part2<R>* xf = part + g.N;
+    if (fx.lo && !(g.wx && x == 0)) {
+        const Part2<R> X = xf[xface_at(g, x / TX, 0, y, z)];
+        dn += X.dn;
+        rc += X.rc;
+    }
+    if (fx.hi && !(g.wx && x == g.nx - 1)) {
+        const Part2<R> X = xf[xface_at(g, x / TX, 1, y, z)];
+        dn += X.dn;
+        rc += X.rc;
+    }
     phi[s] = dn / rc;
 }
 
@@ -177,14 +250,84 @@ template <typename R, int TX, int TY>
 __host__ __device__ constexpr size_t xch_bytes() {
     return (size_t)2 * kXchDirs * TX * TY * sizeof(R);
 }
+// x-face sums an edge lane of a tile column accumulates for the face sites of
+// the neighbouring column: the lo edge lane (SX = -1) feeds the hi face of
+// the column on its left, the hi edge lane (SX = +1) the lo face of the one
+// on its right (periodic wrap; none beyond an x wall).  The running sums of
+// the destination planes z-1, z, z+1 of its row live in LDS, vs[side][plane
+// mod 3][row].
+template <int TX>
+__device__ __forceinline__ bool xface_dest(const Geom& g, int x0, int x1, int SX, int& bd) {
+    if (SX < 0) {
+        if (x0 > 0) {
+            bd = x0 / TX - 1;
+            return true;
+        }
+        bd = (g.nx + TX - 1) / TX - 1;
+        return !g.wx;
+    }
+    if (x1 < g.nx) {
+        bd = x0 / TX + 1;
+        return true;
+    }
+    bd = 0;
+    return !g.wx;
+}
+
+// Before the exchange barrier: the lane's own terms of plane cz close the
+// sum of destination plane cz - 1 (stored), add the first in-plane term of
+// plane cz and open the sum of plane cz + 1.
+template <typename R, int TY, int SX>
+__device__ __forceinline__ void xedge_own(const Geom& g, const R (&t)[Q], const R (&d)[Q], Part2<R>* __restrict__ vs,
+                                          int ty, int y, int cz, int za, int zb, int bd, Part2<R>* __restrict__ xf) {
+    constexpr int im = dir_of(SX, 0, -1), i0 = dir_of(SX, 0, 0), ip = dir_of(SX, 0, 1);
+    constexpr int side = SX < 0 ? 0 : 1;
+    Part2<R>* v = vs + side * 3 * TY + ty;
+    if (cz - 1 >= za) {
+        Part2<R> P = v[((cz - 1 - za) % 3) * TY];
+        P.rc += weight<R>(im) + t[im];
+        P.dn += d[im];
+        xf[xface_at(g, bd, 1 - side, y, cz - 1)] = P;
+    }
+    Part2<R> P = cz == za ? Part2<R>{R(0), R(0)} : v[((cz - za) % 3) * TY];
+    P.rc += weight<R>(i0) + t[i0];
+    P.dn += d[i0];
+    v[((cz - za) % 3) * TY] = P;
+    if (cz + 1 < zb) v[((cz + 1 - za) % 3) * TY] = Part2<R>{R(0) + d[ip], R(0) + (weight<R>(ip) + t[ip])};
+}
+
+// After the exchange barrier: the in-plane terms from the rows above and
+// below (ascending direction); the chunk's last plane is then complete.
+template <typename R, int TX, int TY, int SX>
+__device__ __forceinline__ void xedge_rows(const Geom& g, const R* __restrict__ xch, Part2<R>* __restrict__ vs, int ty,
+                                           int tx, int nrows, int y, int cz, int za, int zb, int bd,
+                                           Part2<R>* __restrict__ xf) {
+    using L = Lattice;
+    constexpr int NT = TX * TY;
+    constexpr int side = SX < 0 ? 0 : 1;
+    Part2<R>* v = vs + side * 3 * TY + ty;
+    Part2<R> P = v[((cz - za) % 3) * TY];
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        if (L::cx[i] != SX || L::cz[i] != 0 || L::cy[i] == 0) continue;
+        const int ys = ty - L::cy[i];
+        if (ys < 0 || ys >= nrows) continue;
+        P.rc += xch[(2 * xch_slot(i)) * NT + ys * TX + tx];
+        P.dn += xch[(2 * xch_slot(i) + 1) * NT + ys * TX + tx];
+    }
+    if (cz == zb - 1) xf[xface_at(g, bd, 1 - side, y, cz)] = P;
+    else v[((cz - za) % 3) * TY] = P;
+}
+
 // One tile of the one-read step: columns [x0, x0+TX) x [y0, y0+TY), planes
 // [za, zb); blockDim.x == TX * TY and TX is the wavefront size.  Every thread
 // of the workgroup must call it (it holds barriers).
 template <typename R, typename Src, typename Dst, int TX, int TY, int H>
 __device__ __forceinline__ void single_tile(const Geom& g, const Src& src, const Dst& dst, const Coeffs<R>& c,
                                             const PhiRing<R, TX, H>& ring, const RecRing<TX>& rr,
-                                            R* __restrict__ xch, int x0, int y0, int za, int zb,
-                                            const R* __restrict__ phi_in, Part2<R>* __restrict__ part_out) {
+                                            R* __restrict__ xch, Part2<R>* __restrict__ vs, int x0, int y0,
+                                            int za, int zb, const R* __restrict__ phi_in,
+                                            Part2<R>* __restrict__ part_out) {
     using L = Lattice;
     constexpr int LX = TX + 2 * H;
     constexpr int NP = 2 * H + 1;
@@ -197,6 +340,11 @@ __device__ __forceinline__ void single_tile(const Geom& g, const Src& src, const
     const int x1 = min(x0 + TX, g.nx), y1 = min(y0 + TY, g.ny);
     Src srcr = src;
     if constexpr (Src::ring) srcr.ring_plane_floats = rr.LY * RecRing<TX>::LX * 8;
+    // edge lanes and the columns their x-face sums go to
+    Part2<R>* const xf = part_out + g.N;
+    int bd_lo = 0, bd_hi = 0;
+    const bool edge_lo = active && tx_ == 0 && xface_dest<TX>(g, x0, x1, -1, bd_lo);
+    const bool edge_hi = active && x_ == x1 - 1 && xface_dest<TX>(g, x0, x1, 1, bd_hi);
     // own sums of the destination planes cz - 1 (prev), cz (cur)
     R prev_dn = R(0), prev_rc = R(0), cur_dn = R(0), cur_rc = R(0);
 
@@ -278,7 +426,11 @@ __device__ __forceinline__ void single_tile(const Geom& g, const Src& src, const
                     sh_d[i] = d[i];
                 }
             }
+            if (edge_lo) xedge_own<R, TY, -1>(g, t, d, vs, ty_, y_, cz, za, zb, bd_lo, xf);
+            if (edge_hi) xedge_own<R, TY, 1>(g, t, d, vs, ty_, y_, cz, za, zb, bd_hi, xf);
             __syncthreads();
+            if (edge_lo) xedge_rows<R, TX, TY, -1>(g, xch, vs, ty_, tx_, y1 - y0, y_, cz, za, zb, bd_lo, xf);
+            if (edge_hi) xedge_rows<R, TX, TY, 1>(g, xch, vs, ty_, tx_, y1 - y0, y_, cz, za, zb, bd_hi, xf);
             if (active) {
                 int x = x_, y = y_, tx = tx_, ty = ty_;
                 asm volatile("" : "+v"(x), "+v"(y), "+v"(tx), "+v"(ty));
@@ -361,9 +513,10 @@ __global__ __launch_bounds__(TX * TY) void single_kernel(Geom g, Src src, Dst ds
     RecRing<TX> rr{reinterpret_cast<f4*>(lds_raw + off), TY + 2};
     if constexpr (Src::ring) off += rec_ring_bytes<TX>(TY);
     R* xch = reinterpret_cast<R*>(lds_raw + off);
+    Part2<R>* vs = reinterpret_cast<Part2<R>*>(lds_raw + off + xch_bytes<R, TX, TY>());
     int x0, y0, za, zb;
     tile_of_block(fs, TX, g.nz, x0, y0, za, zb);
-    single_tile<R, Src, Dst, TX, TY, H>(g, src, dst, c, ring, rr, xch, x0, y0, za, zb, phi_in, part_out);
+    single_tile<R, Src, Dst, TX, TY, H>(g, src, dst, c, ring, rr, xch, vs, x0, y0, za, zb, phi_in, part_out);
 }
 
 }  // namespace lbm
