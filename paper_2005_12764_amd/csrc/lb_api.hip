@@ -121,7 +121,7 @@ struct lb_t {
     void* buf[2];      // post-collision populations, ping-pong
     void* pending;     // raw FP32 state of a 16-bit lattice before its first step
     void* phi;         // phase field of the two-pass step (double for F64, float otherwise)
-    void* part[2];     // own phase sums of the one-read step, ping-pong
+    void* part[2];     // phase sums and phase field of the one-read step, ping-pong
     int part_cur;      // part[part_cur] belongs to the current state ...
     bool part_valid;   // ... when this is set
     Neu* partial;      // reduction partials
@@ -193,7 +193,7 @@ int64_t lb_footprint_bytes(const lb_params* p) {
     // phase sums of the one-read step (raw storage unless two passes are asked
     // for; an upper bound for lattices the automatic choice steps otherwise)
     if (p->storage <= LB_STORE_F32 && p->kernel != LB_KERNEL_TWOPASS)
-        b += 2 * 2 * part_entries<kTX>(p->nx, p->ny, p->nz) * real;
+        b += 2 * part_reals<kTX>(p->nx, p->ny, p->nz) * real;
     return (int64_t)b;
 }
 
@@ -230,8 +230,7 @@ int lb_create(const lb_params* params, void* hip_stream, lb_t** out) {
         return rc;
     }
     if (h->kernel == LB_KERNEL_FUSED) {
-        const size_t pbytes =
-            2 * part_entries<kTX>(h->p.nx, h->p.ny, h->p.nz) * (h->p.storage == LB_STORE_F64 ? 8 : 4);
+        const size_t pbytes = part_reals<kTX>(h->p.nx, h->p.ny, h->p.nz) * (h->p.storage == LB_STORE_F64 ? 8 : 4);
         if ((rc = check_hip(hipMalloc(&h->part[0], pbytes), "hipMalloc phase sums")) ||
             (rc = check_hip(hipMalloc(&h->part[1], pbytes), "hipMalloc phase sums"))) {
             release(h);

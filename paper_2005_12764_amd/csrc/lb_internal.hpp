@@ -22,8 +22,8 @@ struct LatticeView {
     void* nxt = nullptr;       // buffer the next step writes
     void* pending = nullptr;   // raw FP32 current state of a 16-bit lattice (else null)
     void* phi = nullptr;       // phase-field scratch of the two-pass step
-    void* part_in = nullptr;   // own phase sums of the current state (one-read step)
-    void* part_out = nullptr;  // own phase sums the one-read step writes for the next state
+    void* part_in = nullptr;   // phase sums and phase field of the current state (one-read step)
+    void* part_out = nullptr;  // the same, written by the one-read step for the next state
     bool part_valid = false;   // part_in holds the current state's sums
     Coeffs<double> cd;
     Coeffs<float> cf;

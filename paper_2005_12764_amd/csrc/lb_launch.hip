@@ -110,10 +110,11 @@ int zmarch(const LatticeView& v, const Src& src, const Dst& dst, const Coeffs<R>
     return set_error(LB_EINVAL, "near-contact range outside the tile kernels' halo");
 }
 
-// One-read step: the own partial sums of the current state come from the
-// previous one-read step, or from part_kernel when no such step made them;
-// assemble_kernel adds the cross-tile terms into phi; the tile kernel
-// collides, streams and gathers the next state's own sums.
+// One-read step: the own partial sums of the current state (and phi where
+// they are complete) come from the previous one-read step, or from
+// part_kernel when no such step made them; assemble_kernel adds the
+// cross-tile terms into phi of the face sites; the tile kernel collides,
+// streams and gathers the next state's sums and interior phi.
 template <typename R, typename Src, typename Dst, int TY, int H>
 int single_h(const LatticeView& v, const Src& src, const Dst& dst, const Coeffs<R>& c, const FusedShape& fs) {
     const size_t lds = tile_lds(*v.p, TILE_SINGLE, TY);
@@ -124,7 +125,7 @@ int single_h(const LatticeView& v, const Src& src, const Dst& dst, const Coeffs<
         if (e != hipSuccess) return set_error(LB_EDEVICE, (std::string("single_kernel LDS: ") + hipGetErrorString(e)).c_str());
     }
     hipLaunchKernelGGL(kern, dim3(fs.nblocks), dim3(kTX * TY), lds, v.stream, v.g, src, dst, c, fs,
-                       (const R*)v.phi, (Part2<R>*)v.part_out);
+                       (const Part2<R>*)v.part_in, (Part2<R>*)v.part_out);
     return launch_status("single_kernel");
 }
 
@@ -137,8 +138,9 @@ int single_ty(const LatticeView& v, const Src& src, const Dst& dst, const Coeffs
         int rc = launch_status("part_kernel");
         if (rc) return rc;
     }
-    hipLaunchKernelGGL((assemble_kernel<R, Src, kTX, TY>), dim3(grid_for(v.g.N)), dim3(kBlock), 0, v.stream, v.g,
-                       src, fs.TZ, (const Part2<R>*)v.part_in, (R*)v.phi);
+    const FaceSet faces = face_set(v.g, kTX, TY, fs.TZ);
+    hipLaunchKernelGGL((assemble_kernel<R, Src, kTX, TY>), dim3(grid_for(faces.row_sites + faces.edge_sites)),
+                       dim3(kBlock), 0, v.stream, v.g, src, faces, (Part2<R>*)v.part_in);
     int rc = launch_status("assemble_kernel");
     if (rc) return rc;
     if (t) (void)hipEventRecord(t->ev[1], v.stream);
@@ -154,7 +156,7 @@ int single_ty(const LatticeView& v, const Src& src, const Dst& dst, const Coeffs
 
 template <typename R, typename Src, typename Dst>
 int single_pass(const LatticeView& v, const Src& src, const Dst& dst, const Coeffs<R>& c, const StepEvents* t) {
-    if (!v.part_in || !v.part_out || !v.phi) return set_error(LB_EINVAL, "one-read step without its phase buffers");
+    if (!v.part_in || !v.part_out) return set_error(LB_EINVAL, "one-read step without its phase buffers");
     const FusedShape fs = tile_shape(*v.p, TILE_SINGLE);
     if (t) (void)hipEventRecord(t->ev[0], v.stream);
     int rc;

@@ -8,7 +8,8 @@
 // lies in the same box ("own" terms): a partial (D_own, Rc_own) per site.
 // The terms whose source lies in another tile ("foreign": only sites on a
 // face of their box have any) are pulled from the population arrays by a
-// light assembly kernel that turns the partial sums into phi.  Each
+// light assembly kernel that turns the partial sums of the face sites into
+// phi; the tile writes phi of every other site itself.  Each
 // population is read from HBM once per step (plus the few foreign ones),
 // instead of once by a phase pass and again by the collide pass.
 //
@@ -39,11 +40,33 @@ struct Part2 {
     R dn, rc;
 };
 
-// Entries of a phase-sum buffer: the N own sums, then the x-face sums of
-// every tile column (2 faces x ny x nz each).
+// A phase-sum buffer holds, for one state: the own sums of the sites on a
+// face of their box (N pairs, indexed by site), the x-face sums of every tile
+// column (2 faces x ny x nz pairs), and the phase field (N values).  The tile
+// kernel writes phi itself for the sites whose every term is its own; the
+// assembly completes the face sites.
 template <int TX>
-__host__ __device__ constexpr size_t part_entries(int nx, int ny, int nz) {
-    return (size_t)nx * ny * nz + (size_t)2 * ((nx + TX - 1) / TX) * ny * nz;
+__host__ __device__ constexpr size_t xface_entries(int nx, int ny, int nz) {
+    return (size_t)2 * ((nx + TX - 1) / TX) * ny * nz;
+}
+// Size of a phase-sum buffer in reals.
+template <int TX>
+__host__ __device__ constexpr size_t part_reals(int nx, int ny, int nz) {
+    return 2 * ((size_t)nx * ny * nz + xface_entries<TX>(nx, ny, nz)) + (size_t)nx * ny * nz;
+}
+// The phase field of a phase-sum buffer.
+template <int TX, typename R>
+__host__ __device__ __forceinline__ R* phi_of(Part2<R>* part, const Geom& g) {
+    return reinterpret_cast<R*>(part + (size_t)g.N + xface_entries<TX>(g.nx, g.ny, g.nz));
+}
+
+// Is the site a face site of its box (some source of its phase sums may lie
+// in another box)?  x % TX, y % TY: position in the tile; za, zb: the chunk.
+template <int TX, int TY>
+__device__ __forceinline__ bool on_face(const Geom& g, int x, int y, int z, int za, int zb) {
+    const int rx = x % TX, ry = y % TY;
+    return rx == 0 || rx == TX - 1 || x == g.nx - 1 || ry == 0 || ry == TY - 1 || y == g.ny - 1 || z == za ||
+           z == zb - 1;
 }
 
 // x-face sum of the site (x, y, z) on the lo (side 0, x = bx * TX) or hi
@@ -119,8 +142,9 @@ __device__ __forceinline__ Part2<R> xface_sum(const Geom& g, const Src& src, con
     return Part2<R>{dn, rc};
 }
 
-// Own partial sums and x-face sums of the current state, for a state that
-// no one-read step produced (initial, imported, or left by a two-pass step).
+// Own partial sums (phi where they are complete) and x-face sums of the
+// current state, for a state that no one-read step produced (initial,
+// imported, or left by a two-pass step).
 template <typename R, typename Src, int TX, int TY>
 __global__ __launch_bounds__(256) void part_kernel(Geom g, Src src, int TZ, Part2<R>* __restrict__ part) {
     using L = Lattice;
@@ -145,7 +169,8 @@ __global__ __launch_bounds__(256) void part_kernel(Geom g, Src src, int TZ, Part
             dn += d;
         }
     }
-    part[s] = Part2<R>{dn, rc};
+    if (on_face<TX, TY>(g, x, y, z, b.z0, b.z1)) part[s] = Part2<R>{dn, rc};
+    else phi_of<TX>(part, g)[s] = dn / rc;
     // x-face sums of this site (beyond an x wall every term is a bounce-back)
     Part2<R>* xf = part + g.N;
     const bool lo = x % TX == 0 && !(g.wx && x == 0);
@@ -208,19 +233,77 @@ __device__ __forceinline__ void foreign_terms(const Geom& g, const Src& src, int
     }
 }
 
-// phi of every site from the own partial sums, the foreign terms of the z
-// and y faces and the x-face sums.
+// Coordinates along an axis of extent n cut into boxes of T, ranked: the
+// face coordinates (first and last of each box) and the inner ones.
+struct AxisFaces {
+    int n, T;
+    __host__ __device__ int nface() const {
+        if (T <= 2) return n;
+        const int r = n % T;
+        return 2 * (n / T) + (r == 0 ? 0 : (r == 1 ? 1 : 2));
+    }
+    __host__ __device__ int face(int k) const {
+        if (T <= 2) return k;
+        const int b = k >> 1, rest = n - b * T, size = rest < T ? rest : T;
+        return b * T + ((k & 1) ? size - 1 : 0);
+    }
+    __host__ __device__ int inner(int m) const { return (m / (T - 2)) * T + m % (T - 2) + 1; }
+};
+
+// The face sites of the boxes, enumerated for the assembly: first every
+// site of the face rows (the rows of a chunk's z faces, then the rows of a
+// tile's y faces in the other planes), then the x-face sites of the
+// remaining rows.
+struct FaceSet {
+    AxisFaces ax, ay, az;
+    int nyf, nyi, nzf, nxf;
+    int row_sites, edge_sites;
+};
+inline FaceSet face_set(const Geom& g, int TX, int TY, int TZ) {
+    FaceSet f;
+    f.ax = AxisFaces{g.nx, TX};
+    f.ay = AxisFaces{g.ny, TY};
+    f.az = AxisFaces{g.nz, TZ};
+    f.nxf = f.ax.nface();
+    f.nyf = f.ay.nface();
+    f.nyi = g.ny - f.nyf;
+    f.nzf = f.az.nface();
+    const int nzi = g.nz - f.nzf;
+    f.row_sites = (f.nzf * g.ny + nzi * f.nyf) * g.nx;
+    f.edge_sites = nzi * f.nyi * f.nxf;
+    return f;
+}
+
+// phi of the face sites from their own partial sums, the foreign terms of
+// the z and y faces and the x-face sums.
 template <typename R, typename Src, int TX, int TY>
-__global__ __launch_bounds__(256) void assemble_kernel(Geom g, Src src, int TZ, const Part2<R>* __restrict__ part,
-                                                       R* __restrict__ phi) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= g.N) return;
+__global__ __launch_bounds__(256) void assemble_kernel(Geom g, Src src, FaceSet fs, Part2<R>* __restrict__ part) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
     int x, y, z;
-    site_xyz(g, s, x, y, z);
+    if (k < fs.row_sites) {
+        const int r = k / g.nx, zrows = fs.nzf * g.ny;
+        x = k - r * g.nx;
+        if (r < zrows) {
+            z = fs.az.face(r / g.ny);
+            y = r - (r / g.ny) * g.ny;
+        } else {
+            const int r2 = r - zrows;
+            z = fs.az.inner(r2 / fs.nyf);
+            y = fs.ay.face(r2 - (r2 / fs.nyf) * fs.nyf);
+        }
+    } else {
+        const int k2 = k - fs.row_sites;
+        if (k2 >= fs.edge_sites) return;
+        const int q = k2 / fs.nxf;
+        x = fs.ax.face(k2 - q * fs.nxf);
+        z = fs.az.inner(q / fs.nyi);
+        y = fs.ay.inner(q - (q / fs.nyi) * fs.nyi);
+    }
+    const int s = site_of(g, x, y, z);
+    const int TZ = fs.az.T, z0 = z - z % TZ;
+    const Faces fx = faces_of<TX>(x, g.nx), fy = faces_of<TY>(y, g.ny), fz = faces_z(z, z0, min(z0 + TZ, g.nz));
     const Part2<R> P = part[s];
     R dn = P.dn, rc = P.rc;
-    const int z0 = z - z % TZ;
-    const Faces fx = faces_of<TX>(x, g.nx), fy = faces_of<TY>(y, g.ny), fz = faces_z(z, z0, min(z0 + TZ, g.nz));
     if (fz.lo || fz.hi) foreign_terms<R, Src, 2>(g, src, s, x, y, z, fy, fz, dn, rc);
     if (fy.lo || fy.hi) foreign_terms<R, Src, 1>(g, src, s, x, y, z, fy, fz, dn, rc);
     const Part2<R>* xf = part + g.N;
@@ -234,7 +317,7 @@ __global__ __launch_bounds__(256) void assemble_kernel(Geom g, Src src, int TZ, 
         dn += X.dn;
         rc += X.rc;
     }
-    phi[s] = dn / rc;
+    phi_of<TX>(part, g)[s] = dn / rc;
 }
 
 // Exchange slot of a direction with c_y != 0 (the in-plane neighbours in
@@ -327,7 +410,7 @@ __device__ __forceinline__ void single_tile(const Geom& g, const Src& src, const
                                             const PhiRing<R, TX, H>& ring, const RecRing<TX>& rr,
                                             R* __restrict__ xch, Part2<R>* __restrict__ vs, int x0, int y0,
                                             int za, int zb, const R* __restrict__ phi_in,
-                                            Part2<R>* __restrict__ part_out) {
+                                            Part2<R>* __restrict__ part_out, R* __restrict__ phi_out) {
     using L = Lattice;
     constexpr int LX = TX + 2 * H;
     constexpr int NP = 2 * H + 1;
@@ -434,6 +517,9 @@ __device__ __forceinline__ void single_tile(const Geom& g, const Src& src, const
             if (active) {
                 int x = x_, y = y_, tx = tx_, ty = ty_;
                 asm volatile("" : "+v"(x), "+v"(y), "+v"(tx), "+v"(ty));
+                // a site on an x or y face of the box keeps its own sums for the assembly
+                const bool face_xy =
+                    tx == 0 || tx == TX - 1 || x == g.nx - 1 || ty == 0 || ty == TY - 1 || y == g.ny - 1;
                 // value of direction i from the source (x - cx, y - cy) in plane cz
                 auto from = [&](int i, R& va, R& vd) {
                     if (L::cy[i] != 0) {
@@ -461,7 +547,9 @@ __device__ __forceinline__ void single_tile(const Geom& g, const Src& src, const
                         prev_rc += va;
                         prev_dn += vd;
                     }
-                    part_out[site_of(g, x, y, cz - 1)] = Part2<R>{prev_dn, prev_rc};
+                    const int sm1 = site_of(g, x, y, cz - 1);
+                    if (cz - 1 == za || face_xy) part_out[sm1] = Part2<R>{prev_dn, prev_rc};
+                    else phi_out[sm1] = prev_dn / prev_rc;
                 }
                 // destination cz: in-plane sources
                 const WallFlags w0 = wall_flags(g, x, y, cz);
@@ -505,7 +593,7 @@ __device__ __forceinline__ void single_tile(const Geom& g, const Src& src, const
 
 template <typename R, typename Src, typename Dst, int TX, int TY, int H>
 __global__ __launch_bounds__(TX * TY) void single_kernel(Geom g, Src src, Dst dst, Coeffs<R> c, FusedShape fs,
-                                                        const R* __restrict__ phi_in,
+                                                        const Part2<R>* __restrict__ part_in,
                                                         Part2<R>* __restrict__ part_out) {
     extern __shared__ unsigned char lds_raw[];
     PhiRing<R, TX, H> ring{reinterpret_cast<R*>(lds_raw), TY + 2 * H};
@@ -516,7 +604,9 @@ __global__ __launch_bounds__(TX * TY) void single_kernel(Geom g, Src src, Dst ds
     Part2<R>* vs = reinterpret_cast<Part2<R>*>(lds_raw + off + xch_bytes<R, TX, TY>());
     int x0, y0, za, zb;
     tile_of_block(fs, TX, g.nz, x0, y0, za, zb);
-    single_tile<R, Src, Dst, TX, TY, H>(g, src, dst, c, ring, rr, xch, vs, x0, y0, za, zb, phi_in, part_out);
+    single_tile<R, Src, Dst, TX, TY, H>(g, src, dst, c, ring, rr, xch, vs, x0, y0, za, zb,
+                                        phi_of<TX>(const_cast<Part2<R>*>(part_in), g), part_out,
+                                        phi_of<TX>(part_out, g));
 }
 
 }  // namespace lbm
