@@ -506,6 +506,85 @@ void orc_step(const double *p, const double *f_in, double *f_out, int nsteps) {
     free(post);
 }
 
+/* ---------------------------------------------------------------------------
+ * Korteweg-tensor diagnostic of the coarse-graining pipeline (Sec. 4.1, the
+ * Korteweg tensor in terms of the Laplacian and the gradient products of the
+ * field, and the projection by block averages).  The field is the phase field
+ * phi of the state; derivatives use the same D3Q19 stencils and the same
+ * mirror rule at walls as the colour gradient.
+ * ------------------------------------------------------------------------- */
+
+/* Phase field phi = (rho_r - rho_b)/(rho_r + rho_b) of the post-streaming
+ * state (Sec. 2, the colour-gradient model's order parameter). */
+void orc_phase_field(const double *p, const double *f, double *phi) {
+    init_tables();
+    prm_t q = unpack(p);
+    size_t N = nsites(&q);
+#pragma omp parallel for schedule(static)
+    for (long long s = 0; s < (long long)N; ++s) {
+        double rr = 0.0, rb = 0.0;
+        for (int i = 0; i < Q; ++i) {
+            rr += f[(size_t)i * N + s];
+            rb += f[(size_t)(Q + i) * N + s];
+        }
+        phi[s] = (rr - rb) / (rr + rb);
+    }
+}
+
+/* K_ab = lam [phi Lap(phi) + |grad phi|^2 / 2] delta_ab - lam d_a phi d_b phi
+ * at every site, with grad phi = (1/c_s^2) sum_i w_i c_i phi(x + c_i) and
+ * Lap(phi) = (2/c_s^2) sum_i w_i [phi(x + c_i) - phi(x)].  K is [6][N] in the
+ * order xx, yy, zz, xy, xz, yz. */
+void orc_korteweg(const double *p, const double *phi, double lam, double *K) {
+    init_tables();
+    prm_t q = unpack(p);
+    size_t N = nsites(&q);
+#pragma omp parallel for schedule(static)
+    for (long long s = 0; s < (long long)N; ++s) {
+        int x, y, z;
+        coords(&q, (size_t)s, &x, &y, &z);
+        double g[3] = {0.0, 0.0, 0.0}, lap = 0.0;
+        for (int i = 1; i < Q; ++i) {
+            int xn = stencil_coord(x + CV[i][0], q.n[0], q.bc[0]);
+            int yn = stencil_coord(y + CV[i][1], q.n[1], q.bc[1]);
+            int zn = stencil_coord(z + CV[i][2], q.n[2], q.bc[2]);
+            double ph = phi[sidx(&q, xn, yn, zn)];
+            for (int a = 0; a < 3; ++a) g[a] += W[i] * ph * CV[i][a];
+            lap += W[i] * (ph - phi[s]);
+        }
+        for (int a = 0; a < 3; ++a) g[a] *= 3.0;
+        lap *= 6.0;
+        double iso = lam * (phi[s] * lap + 0.5 * (g[0] * g[0] + g[1] * g[1] + g[2] * g[2]));
+        K[0 * N + s] = iso - lam * g[0] * g[0];
+        K[1 * N + s] = iso - lam * g[1] * g[1];
+        K[2 * N + s] = iso - lam * g[2] * g[2];
+        K[3 * N + s] = -lam * g[0] * g[1];
+        K[4 * N + s] = -lam * g[0] * g[2];
+        K[5 * N + s] = -lam * g[1] * g[2];
+    }
+}
+
+/* Projection of ncomp fields [ncomp][N] onto blocks of b x b x b sites
+ * (Sec. 4.1, averaging over blocks): out[c][zc][yc][xc] is the mean over the
+ * block's sites.  Every extent must be a multiple of b. */
+void orc_block_average(const double *p, const double *field, int ncomp, int b, double *out) {
+    prm_t q = unpack(p);
+    size_t N = nsites(&q);
+    int nxc = q.n[0] / b, nyc = q.n[1] / b, nzc = q.n[2] / b;
+    size_t Nc = (size_t)nxc * nyc * nzc;
+    for (int c = 0; c < ncomp; ++c)
+        for (int zc = 0; zc < nzc; ++zc)
+            for (int yc = 0; yc < nyc; ++yc)
+                for (int xc = 0; xc < nxc; ++xc) {
+                    double sum = 0.0;
+                    for (int k = 0; k < b; ++k)
+                        for (int j = 0; j < b; ++j)
+                            for (int i = 0; i < b; ++i)
+                                sum += field[(size_t)c * N + sidx(&q, xc * b + i, yc * b + j, zc * b + k)];
+                    out[(size_t)c * Nc + ((size_t)zc * nyc + yc) * nxc + xc] = sum / ((double)b * b * b);
+                }
+}
+
 /* Number of host threads the parallel loops use (1 without OpenMP). */
 #ifdef _OPENMP
 #include <omp.h>

@@ -66,6 +66,9 @@ def lib():
         L.orc_collide.argtypes = [dp, dp, dp, dp, dp, dp]
         L.orc_stream.argtypes = [dp, dp, dp]
         L.orc_step.argtypes = [dp, dp, dp, ctypes.c_int]
+        L.orc_phase_field.argtypes = [dp, dp, dp]
+        L.orc_korteweg.argtypes = [dp, dp, ctypes.c_double, dp]
+        L.orc_block_average.argtypes = [dp, dp, ctypes.c_int, ctypes.c_int, dp]
         L.orc_threads.restype = ctypes.c_int
         L.orc_set_threads.argtypes = [ctypes.c_int]
         _lib = L
@@ -183,6 +186,32 @@ def phase_gradient(prm: Params, phi):
     G = np.zeros((3,) + prm.shape)
     lib().orc_phase_gradient(_p(prm.vec()), _p(_f64(phi)), _p(G))
     return G
+
+
+def phase_field(prm: Params, f):
+    phi = np.zeros(prm.shape)
+    lib().orc_phase_field(_p(prm.vec()), _p(_f64(f)), _p(phi))
+    return phi
+
+
+def korteweg(prm: Params, phi, lam: float):
+    """Korteweg tensor of the field phi, (6, nz, ny, nx): xx, yy, zz, xy, xz, yz."""
+    K = np.zeros((6,) + prm.shape)
+    lib().orc_korteweg(_p(prm.vec()), _p(_f64(phi)), float(lam), _p(K))
+    return K
+
+
+def block_average(prm: Params, field, b: int):
+    """Means over b x b x b blocks of (ncomp, nz, ny, nx) or (nz, ny, nx) fields."""
+    a = _f64(field)
+    one = a.ndim == 3
+    a = a.reshape((1,) + prm.shape) if one else a
+    nz, ny, nx = prm.shape
+    if nx % b or ny % b or nz % b:
+        raise ValueError("lattice extents must be multiples of the block size")
+    out = np.zeros((a.shape[0], nz // b, ny // b, nx // b))
+    lib().orc_block_average(_p(prm.vec()), _p(np.ascontiguousarray(a)), a.shape[0], int(b), _p(out))
+    return out[0] if one else out
 
 
 def nearcontact(prm: Params, G):
