@@ -223,6 +223,36 @@ def config_c4(args, stream):
             "steps": marks[-1], "results": res}
 
 
+def korteweg_leg(w, stream, b=4, reps=20):
+    """The Korteweg-tensor diagnostic on the FP32 lattice of the workload: phase
+    field of the state, K at every site, block averages over b^3 (device outputs)."""
+    import torch
+    from paper_2005_12764_amd import lb
+
+    L = lb.Lattice(dict(w.params, storage=1), stream=stream)
+    try:
+        L.init(w.rho_r, w.rho_b)
+        L.step(2)
+        nz, ny, nx = w.shape
+        K = torch.empty((6, nz // b, ny // b, nx // b), dtype=torch.float32, device="cuda")
+        P = torch.empty((nz // b, ny // b, nx // b), dtype=torch.float32, device="cuda")
+        lb.lb_korteweg(L.h, 1.0, b, K, P)
+        torch.cuda.synchronize()
+        start = torch.cuda.Event(enable_timing=True)
+        stop = torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        for _ in range(reps):
+            lb.lb_korteweg(L.h, 1.0, b, K, P)
+        stop.record(stream)
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(stop) / reps
+        ok = bool(torch.isfinite(K).all().item() and torch.isfinite(P).all().item())
+        return {"b": b, "ms_per_call": round(ms, 4), "mlups": round(w.sites / (ms * 1e-3) / 1e6, 1),
+                "finite": ok, "field": "phase field of the FP32 state (phase pass + tensor-and-block kernel)"}
+    finally:
+        L.close()
+
+
 def cpu_baseline(w, steps, steps_1t):
     from oracle import oracle as O
     from tests.helpers import oracle_params
@@ -264,6 +294,7 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=40.0)
     ap.add_argument("--serve-steps", type=int, default=500)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-korteweg", action="store_true", help="skip the Korteweg-diagnostic leg")
     ap.add_argument("--config", default="c2", help="c2 (headline), c3 (crystal channel), c4 (spinodal)")
     ap.add_argument("--c-steps", type=int, default=0, help="steps of the c3/c4 runs (0 = the config's)")
     ap.add_argument("--c4-n", type=int, default=384)
@@ -336,6 +367,11 @@ def main():
     roof["copy_gbs"] = round(copy_gbs, 1)
     roof["frac_of_copy"] = round(achieved / copy_gbs, 4)
 
+    kort = None
+    if not args.no_korteweg:
+        kort = korteweg_leg(w, stream)
+        log("korteweg: %s" % kort)
+
     serve_out = None
     if args.serve_jobs > 0:
         serve_out = serving(reqs, prep, args.serve_rate, args.serve_steps, 0.8 * 288)
@@ -373,6 +409,7 @@ def main():
                          "pass_ms": [round(x, 4) for x in v["pass_ms"]],
                          "finite": v["finite"]} for k, v in results.items()},
         "roofline": roof,
+        "korteweg": kort,
         "serving": serve_out,
         "cpu_baseline": cpu,
     }

@@ -151,6 +151,27 @@ int lb_step_timed(lb_t* h, int32_t n, double kernel_ms[3]);
 int lb_moments(lb_t* h, void* rho_r, void* rho_b, void* mom, int32_t dtype, int32_t on_device,
                double totals[14]);
 
+/* Korteweg-tensor diagnostic of the coarse-graining pipeline (Sec. 4.1: the
+ * Korteweg tensor from the Laplacian and gradient products of the field, and
+ * the projection of fine data by block averages).  The field is the phase
+ * field phi = (rho_r - rho_b)/(rho_r + rho_b) of the current state, as the
+ * next collision sees it; at every site
+ *   K_ab = lambda [phi Lap(phi) + |grad phi|^2 / 2] delta_ab - lambda d_a phi d_b phi
+ * with grad phi = 3 sum_i w_i c_i phi(x + c_i) and
+ * Lap(phi) = 6 sum_i w_i (phi(x + c_i) - phi(x)), sites beyond a wall replaced
+ * by their mirror images.  K and phi are averaged over blocks of b x b x b
+ * sites (b = 1, 2, 4 or 8, dividing every extent).
+ * k_blocks: 6 x Nc values (xx, yy, zz, xy, xz, yz, each [nz/b][ny/b][nx/b]);
+ * phi_blocks: Nc values; either may be NULL, not both; dtype LB_DTYPE_F64 or
+ * LB_DTYPE_F32; on_device selects device (caller's stream order) or host
+ * buffers.  accumulate != 0 adds to the outputs instead of overwriting them
+ * (device outputs only), so that b calls over b consecutive steps give the
+ * space-time block of B = b^4 values once divided by b.  Uses the handle's
+ * phase-field scratch; allocates only when staging host outputs.
+ * Errors: LB_EINVAL (arguments), LB_ESTATE (before lb_init_fields). */
+int lb_korteweg(lb_t* h, double lambda, int32_t b, void* k_blocks, void* phi_blocks, int32_t dtype,
+                int32_t on_device, int32_t accumulate);
+
 /* Export the populations f_i(x, t) (post-streaming state) as [2][19][N]
  * values of the given dtype.  For 16-bit storage these are the decoded values. */
 int lb_get_state(lb_t* h, void* f, int32_t dtype, int32_t on_device);

@@ -452,6 +452,40 @@ int lb_moments(lb_t* h, void* rho_r, void* rho_b, void* mom, int32_t dtype, int3
     return rc;
 }
 
+int lb_korteweg(lb_t* h, double lambda, int32_t b, void* k_blocks, void* phi_blocks, int32_t dtype,
+                int32_t on_device, int32_t accumulate) {
+    if (!h) return fail(LB_EINVAL, "handle is NULL");
+    if (!h->initialised) return fail(LB_ESTATE, "lb_korteweg before lb_init_fields");
+    if (dtype != LB_DTYPE_F64 && dtype != LB_DTYPE_F32) return fail(LB_EINVAL, "bad dtype");
+    if (!k_blocks && !phi_blocks) return fail(LB_EINVAL, "no output");
+    if (b != 1 && b != 2 && b != 4 && b != 8) return fail(LB_EINVAL, "block size must be 1, 2, 4 or 8");
+    if (h->p.nx % b || h->p.ny % b || h->p.nz % b) return fail(LB_EINVAL, "lattice extents are not multiples of b");
+    if (accumulate && !on_device) return fail(LB_EINVAL, "accumulation needs device outputs");
+    if (!std::isfinite(lambda)) return fail(LB_EINVAL, "lambda must be finite");
+    const size_t Nc = (size_t)(h->p.nx / b) * (h->p.ny / b) * (h->p.nz / b);
+    const size_t es = dtype == LB_DTYPE_F64 ? 8 : 4;
+    LatticeView v = view_of(h);
+    void* scratch = nullptr;
+    if (!on_device) {
+        int rc = check_hip(hipMalloc(&scratch, 7 * Nc * es), "hipMalloc staging");
+        if (rc) return rc;
+    }
+    void* ko = k_blocks ? (on_device ? k_blocks : scratch) : nullptr;
+    void* po = phi_blocks ? (on_device ? phi_blocks : (char*)scratch + 6 * Nc * es) : nullptr;
+    int rc = launch_korteweg(v, lambda, b, ko, po, dtype, accumulate);
+    if (!rc && !on_device) {
+        if (k_blocks) rc = check_hip(hipMemcpyAsync(k_blocks, ko, 6 * Nc * es, hipMemcpyDeviceToHost, h->stream), "D2H");
+        if (!rc && phi_blocks)
+            rc = check_hip(hipMemcpyAsync(phi_blocks, po, Nc * es, hipMemcpyDeviceToHost, h->stream), "D2H");
+        if (!rc) rc = check_hip(hipStreamSynchronize(h->stream), "sync");
+    }
+    if (scratch) {
+        (void)hipStreamSynchronize(h->stream);
+        (void)hipFree(scratch);
+    }
+    return rc;
+}
+
 int lb_get_state(lb_t* h, void* f, int32_t dtype, int32_t on_device) {
     if (!h || !f) return fail(LB_EINVAL, "NULL argument");
     if (!h->initialised) return fail(LB_ESTATE, "lb_get_state before lb_init_fields");

@@ -57,6 +57,7 @@ int launch_init(const LatticeView& v, const void* rr, const void* rb, const void
 int launch_import(const LatticeView& v, const void* f, int dtype);
 int launch_export(const LatticeView& v, void* out, int dtype);
 int launch_moments(const LatticeView& v, void* rr, void* rb, void* j, int dtype);
+int launch_korteweg(const LatticeView& v, double lam, int b, void* kout, void* pout, int dtype, int accumulate);
 int launch_totals(const LatticeView& v, Neu* partial, double* dtot);
 int launch_droplets(hipStream_t st, const Geom& g, const double* cen, const double* rad, int n, double width,
                     double background, double rho0, double* rr, double* rb);

@@ -8,6 +8,7 @@
 #include <type_traits>
 
 #include "lb_internal.hpp"
+#include "lb_korteweg.hpp"
 #include "lb_single.hpp"
 
 namespace lbm {
@@ -392,6 +393,23 @@ int launch_moments(const LatticeView& v, void* rr, void* rb, void* j, int dtype)
             hipLaunchKernelGGL((moments_kernel<R, S, float>), dim3(grid), dim3(kBlock), 0, v.stream, v.g, src,
                                (float*)rr, (float*)rb, (float*)j);
         return launch_status("moments_kernel");
+    });
+}
+
+int launch_korteweg(const LatticeView& v, double lam, int b, void* kout, void* pout, int dtype, int accumulate) {
+    return with_state(v, [&](auto rt, auto src, const auto&) {
+        using R = decltype(rt);
+        // phase field of the current state (as the next collision sees it) into the scratch field
+        int rc = phase_pass<R>(v, src);
+        if (rc) return rc;
+        const dim3 grid((unsigned)((v.g.nx + 63) / 64), (unsigned)(v.g.ny / b), (unsigned)(v.g.nz / b));
+        if (dtype == LB_DTYPE_F64)
+            hipLaunchKernelGGL((korteweg_kernel<R, double>), grid, dim3(64 * b), 0, v.stream, v.g, (const R*)v.phi,
+                               R(lam), b, (double*)kout, (double*)pout, accumulate);
+        else
+            hipLaunchKernelGGL((korteweg_kernel<R, float>), grid, dim3(64 * b), 0, v.stream, v.g, (const R*)v.phi,
+                               R(lam), b, (float*)kout, (float*)pout, accumulate);
+        return launch_status("korteweg_kernel");
     });
 }
 

@@ -99,6 +99,7 @@ def lib():
         "lb_init_fields": ([vp, vp, vp, vp, i32, i32], i32),
         "lb_step": ([vp, i32], i32),
         "lb_moments": ([vp, vp, vp, vp, i32, i32, dp], i32),
+        "lb_korteweg": ([vp, ctypes.c_double, i32, vp, vp, i32, i32, i32], i32),
         "lb_step_timed": ([vp, i32, dp], i32),
         "lb_get_state": ([vp, vp, i32, i32], i32),
         "lb_set_state": ([vp, vp, i32, i32], i32),
@@ -239,6 +240,26 @@ def lb_moments(h, rho_r=None, rho_b=None, mom=None, want_totals: bool = False):
         t = np.array(tot[:], dtype=np.float64).reshape(7, 2)
         return t
     return None
+
+
+def lb_korteweg(h, lam: float, b: int, k_blocks=None, phi_blocks=None, accumulate: bool = False) -> None:
+    """Block averages of the Korteweg tensor (6, nz/b, ny/b, nx/b) and of phi
+    (nz/b, ny/b, nx/b) into the given outputs (numpy host or torch device,
+    same dtype; either may be None)."""
+    code, dev, ptrs = DTYPE_F64, 0, []
+    for o in (k_blocks, phi_blocks):
+        if o is None:
+            ptrs.append(None)
+            continue
+        if _is_torch(o):
+            p, dev, code, _ = _arg(o)
+        else:
+            if not (isinstance(o, np.ndarray) and o.flags.c_contiguous):
+                raise ValueError("host outputs must be C-contiguous numpy arrays")
+            code = DTYPE_F64 if o.dtype == np.float64 else DTYPE_F32
+            p = ctypes.c_void_p(o.ctypes.data)
+        ptrs.append(p)
+    _check(lib().lb_korteweg(h, float(lam), int(b), ptrs[0], ptrs[1], code, dev, int(bool(accumulate))))
 
 
 def lb_get_state(h, out) -> None:
@@ -393,6 +414,14 @@ class Lattice:
 
     def totals(self):
         return lb_moments(self.h, want_totals=True)
+
+    def korteweg(self, lam: float, b: int):
+        """Host FP64 block averages of the Korteweg tensor and of phi."""
+        nz, ny, nx = self.shape
+        K = np.empty((6, nz // b, ny // b, nx // b))
+        phi = np.empty((nz // b, ny // b, nx // b))
+        lb_korteweg(self.h, lam, b, K, phi)
+        return K, phi
 
     def state(self, dtype=np.float64):
         out = np.empty((2, Q) + self.shape, dtype=dtype)

@@ -1,0 +1,107 @@
+"""GPU parity of the Korteweg-tensor diagnostic (lb_korteweg) with the oracle:
+block averages of K_ab and phi over b^3 blocks (Sec. 4.1)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2005_12764_amd import lb
+from paper_2005_12764_amd import workloads as W
+from tests.helpers import oracle_params
+
+pytestmark = pytest.mark.gpu
+
+
+def _field(nx, ny, nz):
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    return 0.8 * np.sin(2 * math.pi * x / nx) * np.sin(4 * math.pi * y / ny) * np.cos(2 * math.pi * z / nz + 0.3)
+
+
+def _oracle_blocks(prm, phi, lam, b):
+    return O.block_average(prm, O.korteweg(prm, phi, lam), b), O.block_average(prm, phi, b)
+
+
+def _rel(a, b):
+    # against the larger of the reference's magnitude and 1 (block means of phi
+    # may cancel to rounding level, while phi itself is of order one)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1.0 if b.ndim == 3 else 1e-300))
+
+
+@pytest.mark.parametrize("b", [1, 2, 4, 8])
+@pytest.mark.parametrize("n,bc", [((24, 16, 8), (0, 0, 0)), ((72, 8, 16), (1, 0, 1))], ids=["periodic", "walls"])
+def test_analytic_field_f64(n, bc, b):
+    nx, ny, nz = n
+    phi = _field(nx, ny, nz)
+    p = W.base_params(nx, ny, nz, bc=bc, storage=W.F64)
+    lam = 0.7
+    with lb.Lattice(p) as L:
+        L.init(0.5 * (1 + phi), 0.5 * (1 - phi))
+        K, pb = L.korteweg(lam, b)
+    Ko, po = _oracle_blocks(oracle_params(p), phi, lam, b)
+    print("korteweg %s b=%d: K %.2e phi %.2e" % (bc, b, _rel(K, Ko), _rel(pb, po)), flush=True)
+    assert K.shape == (6, nz // b, ny // b, nx // b)
+    assert _rel(K, Ko) < 1e-12 and _rel(pb, po) < 1e-13
+
+
+@pytest.mark.parametrize("storage,tol", [(W.F64, 1e-11), (W.F32, 2e-5)])
+def test_evolved_droplets_against_oracle(storage, tol):
+    w = W.two_droplets(n=(40, 24, 16), R=6, gap=2.0, A=0.01, nc_strength=0.03, nc_range=2)
+    w.params["bc"] = (0, 1, 1)
+    p = dict(w.params, storage=storage)
+    with lb.Lattice(p) as L:
+        L.init(w.rho_r, w.rho_b).step(30)
+        K, pb = L.korteweg(0.5, 4)
+    prm = oracle_params(p)
+    f = O.step(prm, O.init(prm, w.rho_r, w.rho_b), 30)
+    Ko, po = _oracle_blocks(prm, O.phase_field(prm, f), 0.5, 4)
+    print("korteweg droplets storage=%d: K %.2e phi %.2e" % (storage, _rel(K, Ko), _rel(pb, po)), flush=True)
+    assert _rel(K, Ko) < tol and _rel(pb, po) < tol
+
+
+def test_device_outputs_and_accumulation():
+    import torch
+    nx, ny, nz = 24, 16, 8
+    phi = _field(nx, ny, nz)
+    p = W.base_params(nx, ny, nz, storage=W.F32)
+    with lb.Lattice(p) as L:
+        L.init(0.5 * (1 + phi), 0.5 * (1 - phi))
+        K1, p1 = L.korteweg(1.5, 2)
+        Kd = torch.zeros((6, nz // 2, ny // 2, nx // 2), dtype=torch.float32, device="cuda")
+        pd = torch.zeros((nz // 2, ny // 2, nx // 2), dtype=torch.float32, device="cuda")
+        lb.lb_korteweg(L.h, 1.5, 2, Kd, pd)
+        torch.cuda.synchronize()
+        one = (Kd.cpu().numpy().copy(), pd.cpu().numpy().copy())
+        lb.lb_korteweg(L.h, 1.5, 2, Kd, pd, accumulate=True)
+        torch.cuda.synchronize()
+        assert np.array_equal(Kd.cpu().numpy(), 2 * one[0]) and np.array_equal(pd.cpu().numpy(), 2 * one[1])
+    # the FP32 device results are the FP64 host results rounded
+    assert np.abs(one[0] - K1).max() <= 1e-6 * np.abs(K1).max() + 1e-12
+    assert np.abs(one[1] - p1).max() <= 1e-6
+
+
+def test_sixteen_bit_lattice_agrees_with_fp32():
+    w = W.two_droplets(n=(40, 24, 16), R=6, gap=2.0, A=0.01, nc_strength=0.03, nc_range=2)
+    out = {}
+    for st in (W.F32, W.F16):
+        with lb.Lattice(dict(w.params, storage=st)) as L:
+            L.init(w.rho_r, w.rho_b).step(10)
+            out[st] = L.korteweg(0.5, 8)
+    assert _rel(out[W.F16][0], out[W.F32][0]) < 1e-3
+    assert _rel(out[W.F16][1], out[W.F32][1]) < 1e-4
+
+
+def test_invalid_arguments():
+    p = W.base_params(24, 16, 8, storage=W.F32)
+    with lb.Lattice(p) as L:
+        L.init(np.full((8, 16, 24), 0.5), np.full((8, 16, 24), 0.5))
+        for bad in (3, 16, 0):
+            with pytest.raises(lb.LbError):
+                lb.lb_korteweg(L.h, 1.0, bad, np.empty(6 * 8 * 16 * 24), None)
+        K = np.empty((6, 1, 1, 1))
+        with pytest.raises(lb.LbError):
+            lb.lb_korteweg(L.h, 1.0, 8, K, None, accumulate=True)   # host outputs cannot accumulate
+    with lb.Lattice(W.base_params(24, 12, 8, storage=W.F32)) as L:
+        L.init(np.full((8, 12, 24), 0.5), np.full((8, 12, 24), 0.5))
+        with pytest.raises(lb.LbError):
+            L.korteweg(1.0, 8)                                      # 12 is not a multiple of 8
