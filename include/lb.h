@@ -17,6 +17,8 @@
  *     colour-gradient models (the paper uses them without writing them out);
  *   - streaming, an exact memory shift (Sec. 2), with periodic axes or halfway
  *     bounce-back walls.
+ * Beside the step, lb_korteweg projects the Korteweg tensor of the phase field
+ * onto blocks, the data step of the coarse-graining proposal (Sec. 4.1).
  * The readings of the paper that the library takes where the text is silent
  * or garbled (sign of w_eff, force split, the discrete near-contact probe,
  * gradient at walls) are documented with the design notes of the repository.
