@@ -248,7 +248,7 @@ def korteweg_leg(w, stream, b=4, reps=20):
         ms = start.elapsed_time(stop) / reps
         ok = bool(torch.isfinite(K).all().item() and torch.isfinite(P).all().item())
         return {"b": b, "ms_per_call": round(ms, 4), "mlups": round(w.sites / (ms * 1e-3) / 1e6, 1),
-                "finite": ok, "field": "phase field of the FP32 state (phase pass + tensor-and-block kernel)"}
+                "finite": ok, "field": "phase field of the one-read FP32 state (face-site assembly + tensor-and-block kernel)"}
     finally:
         L.close()
 

@@ -5,83 +5,117 @@
 // with the D3Q19 stencils grad phi = 3 sum_i w_i c_i phi(x + c_i) and
 // Lap(phi) = 6 sum_i w_i (phi(x + c_i) - phi(x)) (mirror sites beyond walls,
 // as for the colour gradient), averaged with phi over blocks of b x b x b
-// sites.  One workgroup covers 64 columns x b rows of one block layer: each
-// thread sums its site's seven values over the b planes of the layer, lanes
-// combine across the b columns of a block by a butterfly of shuffles, and the
-// first wavefront adds the b rows in order, so every result is reproducible.
+// sites.
+//
+// One workgroup covers 64 columns x 8 rows and marches a chunk of planes,
+// the phase field of four planes (tile plus a one-site halo) in an LDS ring,
+// so each value is read from HBM about once.  Each thread sums its column's
+// seven values over the b planes of a block layer; at the end of a layer the
+// lanes combine the b columns of a block by a butterfly of shuffles and the
+// first wavefront adds the block's b rows in order, so every result is
+// reproducible.
 #pragma once
 #include "lb_kernels.hpp"
 
 namespace lbm {
 
-constexpr int kKortewegMaxB = 8;
+constexpr int kKortewegRows = 8;    // rows of a workgroup (a multiple of every b)
+constexpr int kKortewegChunk = 32;  // planes a workgroup marches (a multiple of every b)
 
 template <typename R, typename Out>
-__global__ __launch_bounds__(64 * kKortewegMaxB) void korteweg_kernel(Geom g, const R* __restrict__ phi, R lam,
+__global__ __launch_bounds__(64 * kKortewegRows) void korteweg_kernel(Geom g, const R* __restrict__ phi, R lam,
                                                                       int b, Out* __restrict__ kout,
                                                                       Out* __restrict__ pout, int accumulate) {
     using L = Lattice;
-    __shared__ R acc[64 * 7];  // [row][block column][value]: b rows x 64/b block columns
+    constexpr int TY = kKortewegRows, LX = 64 + 2, LY = TY + 2, NP = 4;
+    __shared__ R ring[NP * LY * LX];
+    __shared__ R acc[TY * 64 * 7];  // [row][block column][value]
     const int lane = threadIdx.x & 63, row = threadIdx.x >> 6;
-    const int x = blockIdx.x * 64 + lane, y = blockIdx.y * b + row;
+    const int x0 = blockIdx.x * 64, y0 = blockIdx.y * TY, za = blockIdx.z * kKortewegChunk;
+    const int zb = min(za + kKortewegChunk, g.nz);
+    const int x = x0 + lane, y = y0 + row;
+    const bool active = x < g.nx && y < g.ny;
+    const int cols = 64 / b;
     R sum[7];
 #pragma unroll
     for (int c = 0; c < 7; ++c) sum[c] = R(0);
-    if (x < g.nx) {
-        for (int z = blockIdx.z * b; z < blockIdx.z * b + b; ++z) {
-            const R p0 = phi[site_of(g, x, y, z)];
+    for (int p = za - 1; p <= zb; ++p) {
+        // stage plane p (tile plus halo) into slot p mod 4
+        {
+            R* dst = ring + ((p + NP) % NP) * (LY * LX);
+            const int zz = stencil_coord(p, g.nz, g.wz);
+            for (int q = threadIdx.x; q < LY * LX; q += 64 * TY) {
+                const int ly = q / LX, lx = q - ly * LX;
+                // coordinates past the first one beyond the lattice only feed
+                // inactive threads: clamp them into the stencil's range
+                const int xx = stencil_coord(min(x0 - 1 + lx, g.nx), g.nx, g.wx);
+                const int yy = stencil_coord(min(y0 - 1 + ly, g.ny), g.ny, g.wy);
+                dst[q] = phi[site_of(g, xx, yy, zz)];
+            }
+        }
+        __syncthreads();
+        const int z = p - 1;
+        if (z < za) continue;
+        // K at (x, y, z) from planes z-1, z, z+1
+        if (active) {
+            const R* pm = ring + ((z - 1 + NP) % NP) * (LY * LX);
+            const R* p0 = ring + ((z + NP) % NP) * (LY * LX);
+            const R* pp = ring + ((z + 1 + NP) % NP) * (LY * LX);
+            const int c0 = (row + 1) * LX + lane + 1;
+            const R f0 = p0[c0];
             R gx = R(0), gy = R(0), gz = R(0), lap = R(0);
 #pragma unroll
             for (int i = 1; i < Q; ++i) {
-                const int xn = L::cx[i] ? stencil_coord(x + L::cx[i], g.nx, g.wx) : x;
-                const int yn = L::cy[i] ? stencil_coord(y + L::cy[i], g.ny, g.wy) : y;
-                const int zn = L::cz[i] ? stencil_coord(z + L::cz[i], g.nz, g.wz) : z;
-                const R pn = phi[site_of(g, xn, yn, zn)];
+                const R* pl = L::cz[i] > 0 ? pp : (L::cz[i] < 0 ? pm : p0);
+                const R pn = pl[c0 + L::cy[i] * LX + L::cx[i]];
                 const R wp = weight<R>(i) * pn;
                 if (L::cx[i]) gx += L::cx[i] > 0 ? wp : -wp;
                 if (L::cy[i]) gy += L::cy[i] > 0 ? wp : -wp;
                 if (L::cz[i]) gz += L::cz[i] > 0 ? wp : -wp;
-                lap += weight<R>(i) * (pn - p0);
+                lap += weight<R>(i) * (pn - f0);
             }
             gx *= R(3);
             gy *= R(3);
             gz *= R(3);
             lap *= R(6);
-            const R iso = lam * (p0 * lap + R(0.5) * (gx * gx + gy * gy + gz * gz));
+            const R iso = lam * (f0 * lap + R(0.5) * (gx * gx + gy * gy + gz * gz));
             sum[0] += iso - lam * gx * gx;
             sum[1] += iso - lam * gy * gy;
             sum[2] += iso - lam * gz * gz;
             sum[3] += -lam * gx * gy;
             sum[4] += -lam * gx * gz;
             sum[5] += -lam * gy * gz;
-            sum[6] += p0;
+            sum[6] += f0;
         }
-    }
-    // the b columns of a block: butterfly over lanes that differ in the low bits
-    for (int m = 1; m < b; m <<= 1) {
+        if ((z - za) % b != b - 1) continue;
+        // a block layer is complete: the b columns, then the b rows of each block
+        for (int m = 1; m < b; m <<= 1) {
 #pragma unroll
-        for (int c = 0; c < 7; ++c) sum[c] += __shfl_xor(sum[c], m, 64);
-    }
-    const int cols = 64 / b;
-    if (lane % b == 0) {
+            for (int c = 0; c < 7; ++c) sum[c] += __shfl_xor(sum[c], m, 64);
+        }
+        if (lane % b == 0) {
 #pragma unroll
-        for (int c = 0; c < 7; ++c) acc[(row * cols + lane / b) * 7 + c] = sum[c];
-    }
-    __syncthreads();
-    if (row == 0 && lane < cols) {
-        const int nxc = g.nx / b, nyc = g.ny / b;
-        const int xc = blockIdx.x * cols + lane;
-        if (xc < nxc) {
-            const size_t Nc = (size_t)nxc * nyc * (g.nz / b);
-            const size_t at = ((size_t)blockIdx.z * nyc + blockIdx.y) * nxc + xc;
-            const R inv = R(1) / R(b * b * b);
+            for (int c = 0; c < 7; ++c) acc[(row * cols + lane / b) * 7 + c] = sum[c];
+        }
 #pragma unroll
-            for (int c = 0; c < 7; ++c) {
-                R v = R(0);
-                for (int r = 0; r < b; ++r) v += acc[(r * cols + lane) * 7 + c];
-                v *= inv;
-                Out* o = c < 6 ? (kout ? kout + c * Nc + at : nullptr) : (pout ? pout + at : nullptr);
-                if (o) *o = accumulate ? Out(*o + Out(v)) : Out(v);
+        for (int c = 0; c < 7; ++c) sum[c] = R(0);
+        __syncthreads();
+        if (threadIdx.x < cols * (TY / b)) {
+            const int bc = threadIdx.x % cols, br = threadIdx.x / cols;  // block column, block row
+            const int nxc = g.nx / b, nyc = g.ny / b;
+            const int xc = x0 / b + bc, yc = y0 / b + br, zc = z / b;
+            if (xc < nxc && yc < nyc) {
+                const size_t Nc = (size_t)nxc * nyc * (g.nz / b);
+                const size_t at = ((size_t)zc * nyc + yc) * nxc + xc;
+                const R inv = R(1) / R(b * b * b);
+#pragma unroll
+                for (int c = 0; c < 7; ++c) {
+                    R v = R(0);
+                    for (int r = 0; r < b; ++r) v += acc[((br * b + r) * cols + bc) * 7 + c];
+                    v *= inv;
+                    Out* o = c < 6 ? (kout ? kout + c * Nc + at : nullptr) : (pout ? pout + at : nullptr);
+                    if (o) *o = accumulate ? Out(*o + Out(v)) : Out(v);
+                }
             }
         }
     }

@@ -130,6 +130,16 @@ int single_h(const LatticeView& v, const Src& src, const Dst& dst, const Coeffs<
     return launch_status("single_kernel");
 }
 
+// phi of the face sites of a one-read state (its interior phi is already in
+// the phase-sum buffer).
+template <typename R, typename Src, int TY>
+int assemble_phase(const LatticeView& v, const Src& src, const FusedShape& fs) {
+    const FaceSet faces = face_set(v.g, kTX, TY, fs.TZ);
+    hipLaunchKernelGGL((assemble_kernel<R, Src, kTX, TY>), dim3(grid_for(faces.row_sites + faces.edge_sites)),
+                       dim3(kBlock), 0, v.stream, v.g, src, faces, (Part2<R>*)v.part_in);
+    return launch_status("assemble_kernel");
+}
+
 template <typename R, typename Src, typename Dst, int TY>
 int single_ty(const LatticeView& v, const Src& src, const Dst& dst, const Coeffs<R>& c, const FusedShape& fs,
               const StepEvents* t) {
@@ -139,10 +149,7 @@ int single_ty(const LatticeView& v, const Src& src, const Dst& dst, const Coeffs
         int rc = launch_status("part_kernel");
         if (rc) return rc;
     }
-    const FaceSet faces = face_set(v.g, kTX, TY, fs.TZ);
-    hipLaunchKernelGGL((assemble_kernel<R, Src, kTX, TY>), dim3(grid_for(faces.row_sites + faces.edge_sites)),
-                       dim3(kBlock), 0, v.stream, v.g, src, faces, (Part2<R>*)v.part_in);
-    int rc = launch_status("assemble_kernel");
+    int rc = assemble_phase<R, Src, TY>(v, src, fs);
     if (rc) return rc;
     if (t) (void)hipEventRecord(t->ev[1], v.stream);
     switch (tile_halo(*v.p)) {
@@ -399,16 +406,31 @@ int launch_moments(const LatticeView& v, void* rr, void* rb, void* j, int dtype)
 int launch_korteweg(const LatticeView& v, double lam, int b, void* kout, void* pout, int dtype, int accumulate) {
     return with_state(v, [&](auto rt, auto src, const auto&) {
         using R = decltype(rt);
-        // phase field of the current state (as the next collision sees it) into the scratch field
-        int rc = phase_pass<R>(v, src);
+        using S = decltype(src);
+        // phase field of the current state, as the next collision sees it: a
+        // one-read state completes the field its phase-sum buffer holds (the
+        // next step repeats that, with the same result); otherwise a phase
+        // pass writes it into the scratch field
+        const R* field = (const R*)v.phi;
+        int rc;
+        if (v.part_valid && v.part_in) {
+            const FusedShape fs = tile_shape(*v.p, TILE_SINGLE);
+            if (fs.TY == kSingleTY) rc = assemble_phase<R, S, kSingleTY>(v, src, fs);
+            else rc = assemble_phase<R, S, kSingleTYSmall>(v, src, fs);
+            field = phi_of<kTX>((Part2<R>*)v.part_in, v.g);
+        } else {
+            rc = phase_pass<R>(v, src);
+        }
         if (rc) return rc;
-        const dim3 grid((unsigned)((v.g.nx + 63) / 64), (unsigned)(v.g.ny / b), (unsigned)(v.g.nz / b));
+        const dim3 grid((unsigned)((v.g.nx + 63) / 64), (unsigned)((v.g.ny + kKortewegRows - 1) / kKortewegRows),
+                        (unsigned)((v.g.nz + kKortewegChunk - 1) / kKortewegChunk));
+        const dim3 block(64 * kKortewegRows);
         if (dtype == LB_DTYPE_F64)
-            hipLaunchKernelGGL((korteweg_kernel<R, double>), grid, dim3(64 * b), 0, v.stream, v.g, (const R*)v.phi,
-                               R(lam), b, (double*)kout, (double*)pout, accumulate);
+            hipLaunchKernelGGL((korteweg_kernel<R, double>), grid, block, 0, v.stream, v.g, field, R(lam),
+                               b, (double*)kout, (double*)pout, accumulate);
         else
-            hipLaunchKernelGGL((korteweg_kernel<R, float>), grid, dim3(64 * b), 0, v.stream, v.g, (const R*)v.phi,
-                               R(lam), b, (float*)kout, (float*)pout, accumulate);
+            hipLaunchKernelGGL((korteweg_kernel<R, float>), grid, block, 0, v.stream, v.g, field, R(lam),
+                               b, (float*)kout, (float*)pout, accumulate);
         return launch_status("korteweg_kernel");
     });
 }

@@ -44,19 +44,35 @@ def test_analytic_field_f64(n, bc, b):
     assert _rel(K, Ko) < 1e-12 and _rel(pb, po) < 1e-13
 
 
-@pytest.mark.parametrize("storage,tol", [(W.F64, 1e-11), (W.F32, 2e-5)])
-def test_evolved_droplets_against_oracle(storage, tol):
+# the one-read step's state carries most of its phase field (completed by the
+# assembly); a two-pass state gets it from a phase pass
+@pytest.mark.parametrize("storage,kernel,tol", [(W.F64, lb.KERNEL_FUSED, 1e-11), (W.F64, lb.KERNEL_TWOPASS, 1e-11),
+                                                (W.F32, lb.KERNEL_FUSED, 2e-5)])
+def test_evolved_droplets_against_oracle(storage, kernel, tol):
     w = W.two_droplets(n=(40, 24, 16), R=6, gap=2.0, A=0.01, nc_strength=0.03, nc_range=2)
     w.params["bc"] = (0, 1, 1)
     p = dict(w.params, storage=storage)
-    with lb.Lattice(p) as L:
+    with lb.Lattice(dict(p, kernel=kernel)) as L:
         L.init(w.rho_r, w.rho_b).step(30)
+        assert L.kernel == kernel
         K, pb = L.korteweg(0.5, 4)
     prm = oracle_params(p)
     f = O.step(prm, O.init(prm, w.rho_r, w.rho_b), 30)
     Ko, po = _oracle_blocks(prm, O.phase_field(prm, f), 0.5, 4)
     print("korteweg droplets storage=%d: K %.2e phi %.2e" % (storage, _rel(K, Ko), _rel(pb, po)), flush=True)
     assert _rel(K, Ko) < tol and _rel(pb, po) < tol
+
+
+@pytest.mark.parametrize("kernel", [lb.KERNEL_FUSED, lb.KERNEL_TWOPASS])
+def test_diagnostic_leaves_the_run_unchanged(kernel):
+    w = W.two_droplets(n=(70, 24, 16), R=6, gap=2.0, A=0.01, nc_strength=0.03, nc_range=2)
+    p = dict(w.params, storage=W.F32, kernel=kernel)
+    with lb.Lattice(p) as A, lb.Lattice(p) as B:
+        A.init(w.rho_r, w.rho_b).step(10)
+        A.korteweg(0.5, 2)
+        A.step(10)
+        B.init(w.rho_r, w.rho_b).step(20)
+        assert np.array_equal(A.state(), B.state())
 
 
 def test_device_outputs_and_accumulation():
