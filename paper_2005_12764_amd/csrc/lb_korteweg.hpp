@@ -39,23 +39,44 @@ __global__ __launch_bounds__(64 * kKortewegRows) void korteweg_kernel(Geom g, co
     R sum[7];
 #pragma unroll
     for (int c = 0; c < 7; ++c) sum[c] = R(0);
-    for (int p = za - 1; p <= zb; ++p) {
-        // stage plane p (tile plus halo) into slot p mod 4
-        {
-            R* dst = ring + ((p + NP) % NP) * (LY * LX);
-            const int zz = stencil_coord(p, g.nz, g.wz);
-            for (int q = threadIdx.x; q < LY * LX; q += 64 * TY) {
+    // the staged window: the tile plus a one-site halo, LY x LX values per
+    // plane; each thread stages the entries q = threadIdx.x + k * 512
+    constexpr int NT = 64 * TY, PER = (LY * LX + NT - 1) / NT;
+    auto load_plane = [&](int p, R (&v)[PER]) {
+        const int zz = stencil_coord(p, g.nz, g.wz);
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int q = threadIdx.x + k * NT;
+            if (q < LY * LX) {
                 const int ly = q / LX, lx = q - ly * LX;
                 // coordinates past the first one beyond the lattice only feed
                 // inactive threads: clamp them into the stencil's range
                 const int xx = stencil_coord(min(x0 - 1 + lx, g.nx), g.nx, g.wx);
                 const int yy = stencil_coord(min(y0 - 1 + ly, g.ny), g.ny, g.wy);
-                dst[q] = phi[site_of(g, xx, yy, zz)];
+                v[k] = phi[site_of(g, xx, yy, zz)];
             }
         }
+    };
+    auto store_plane = [&](int p, const R (&v)[PER]) {
+        R* dst = ring + ((p + NP) % NP) * (LY * LX);
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int q = threadIdx.x + k * NT;
+            if (q < LY * LX) dst[q] = v[k];
+        }
+    };
+    R nxt[PER];
+    load_plane(za - 1, nxt);
+    store_plane(za - 1, nxt);
+    load_plane(za, nxt);
+    store_plane(za, nxt);
+    load_plane(za + 1, nxt);
+    for (int z = za; z < zb; ++z) {
+        // LDS holds planes z-1 and z; plane z+1 arrives from registers, and
+        // the loads of plane z+2 are in flight while plane z is computed
+        store_plane(z + 1, nxt);
         __syncthreads();
-        const int z = p - 1;
-        if (z < za) continue;
+        if (z + 2 <= zb) load_plane(z + 2, nxt);
         // K at (x, y, z) from planes z-1, z, z+1
         if (active) {
             const R* pm = ring + ((z - 1 + NP) % NP) * (LY * LX);
