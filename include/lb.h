@@ -74,6 +74,12 @@ extern "C" {
                                step.  Lattices with moving walls step with two passes
                                after their first step. */
 
+/* Tile kinds of lb_set_tiles. */
+#define LB_TILES_PHASE 0    /* phase-field pass of two-pass steps (16-bit storage) */
+#define LB_TILES_COLLIDE 1  /* collide-and-stream pass of two-pass steps */
+#define LB_TILES_ONE_READ 2 /* one-read step (rows 4 or 8) */
+#define LB_TILES_BATCH 3    /* both passes of the batched step (rows 1, 2, 4 or 8) */
+
 /* Element type of caller fields. */
 #define LB_DTYPE_F64 0
 #define LB_DTYPE_F32 1
@@ -199,6 +205,20 @@ int lb_destroy(lb_t* h);
 
 /* Message of the calling thread's last failure ("" if none). */
 const char* lb_last_error(void);
+
+/* Tile shape of one kind of tile kernel for one storage type, for this
+ * process: rows ty of a 64-wide tile and planes tz of the z chunk a workgroup
+ * marches; 0 leaves the library's choice (measured defaults, or the
+ * LB_*_TY / LB_*_TZ environment variables).  Lattices take the setting at
+ * each step (a one-read lattice whose tile shape changed re-sums its phase
+ * field before its next step); a batch takes it at lb_batch_create.  Rows
+ * that do not fit the LDS budget are halved until they do.  For tools that
+ * time tile shapes (the package's autotuner) and for callers applying their
+ * results.  Results of two-pass and batched steps do not depend on the tile
+ * shape; the one-read step's phase sums follow its tile boxes, so its results
+ * move by rounding.  Not thread-safe against concurrent steps.
+ * Errors: LB_EINVAL (unknown kind or storage, ty or tz out of range). */
+int lb_set_tiles(int32_t kind, int32_t storage, int32_t ty, int32_t tz);
 
 /* Bytes of device memory a lattice with these parameters holds. */
 int64_t lb_footprint_bytes(const lb_params* params);

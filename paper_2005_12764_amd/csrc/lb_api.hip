@@ -124,6 +124,7 @@ struct lb_t {
     void* part[2];     // phase sums and phase field of the one-read step, ping-pong
     int part_cur;      // part[part_cur] belongs to the current state ...
     bool part_valid;   // ... when this is set
+    int part_ty = 0, part_tz = 0;  // tile boxes those sums follow
     Neu* partial;      // reduction partials
     double* dtot;      // device totals [14]
     int cur;           // buffer holding the current state
@@ -149,7 +150,13 @@ lbm::LatticeView view_of(lb_t* h) {
     v.phi = h->phi;
     v.part_in = h->part[h->part_cur];
     v.part_out = h->part[h->part_cur ^ 1];
-    v.part_valid = h->part_valid;
+    // sums gathered for other tile boxes than the next step's are summed again
+    if (h->part_valid) {
+        const lbm::FusedShape fs = lbm::tile_shape(h->p, lbm::TILE_SINGLE);
+        v.part_valid = fs.TY == h->part_ty && fs.TZ == h->part_tz;
+    } else {
+        v.part_valid = false;
+    }
     v.cd = h->cd;
     v.cf = h->cf;
     return v;
@@ -183,6 +190,18 @@ int copy_in(const void* src, int on_device, size_t bytes, void** dev_out, void* 
 extern "C" {
 
 const char* lb_last_error(void) { return g_err.c_str(); }
+
+int lb_set_tiles(int32_t kind, int32_t storage, int32_t ty, int32_t tz) {
+    static const int kind_of[4] = {TILE_PHASE, TILE_COLLIDE, TILE_SINGLE, TILE_BATCH};
+    if (kind < LB_TILES_PHASE || kind > LB_TILES_BATCH) return fail(LB_EINVAL, "unknown tile kind");
+    if (storage < LB_STORE_F64 || storage > LB_STORE_BF16) return fail(LB_EINVAL, "unknown storage");
+    const bool rows_ok = kind == LB_TILES_ONE_READ ? (ty == 0 || ty == 4 || ty == 8)
+                                                   : (ty == 0 || ty == 1 || ty == 2 || ty == 4 || ty == 8 || ty == 16);
+    if (!rows_ok || (kind == LB_TILES_BATCH && ty == 16)) return fail(LB_EINVAL, "tile rows not supported for this kind");
+    if (tz < 0 || tz > 4096) return fail(LB_EINVAL, "tile planes outside 0..4096");
+    set_tile_setting(kind_of[kind], storage, ty, tz);
+    return LB_OK;
+}
 
 int64_t lb_footprint_bytes(const lb_params* p) {
     std::string why;
@@ -352,8 +371,11 @@ static int advance(lb_t* h, const StepEvents* t, int* used) {
     h->steps++;
     h->fresh = false;
     if (kernel == LB_KERNEL_FUSED) {
+        const FusedShape fs = tile_shape(h->p, TILE_SINGLE);
         h->part_cur ^= 1;
         h->part_valid = true;
+        h->part_ty = fs.TY;
+        h->part_tz = fs.TZ;
     } else {
         h->part_valid = false;
     }

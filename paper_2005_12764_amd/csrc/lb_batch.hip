@@ -157,17 +157,17 @@ __global__ void batch_tick_kernel(long long* gstep) {
     if (blockIdx.x == 0 && threadIdx.x == 0) gstep[0] = gstep[0] + 1;
 }
 
+// Default tile rows of the batched passes (measured on MI355X).
 int batch_rows(int storage) { return storage == LB_STORE_F64 ? 8 : 4; }
 
-size_t batch_phase_lds(int storage) {
-    return storage >= LB_STORE_F16 ? rec_ring_bytes<kBatchTX>(batch_rows(storage)) : 0;
+size_t batch_phase_lds(int storage, int TY) {
+    return storage >= LB_STORE_F16 ? rec_ring_bytes<kBatchTX>(TY) : 0;
 }
 
-size_t batch_collide_lds(int storage) {
-    const int TY = batch_rows(storage);
+size_t batch_collide_lds(int storage, int TY) {
     const size_t phi = storage == LB_STORE_F64 ? phi_ring_bytes<double, kBatchTX, kBatchH>(TY)
                                                : phi_ring_bytes<float, kBatchTX, kBatchH>(TY);
-    return ((phi + 15) & ~size_t(15)) + batch_phase_lds(storage);
+    return ((phi + 15) & ~size_t(15)) + batch_phase_lds(storage, TY);
 }
 
 }  // namespace lbm
@@ -263,6 +263,7 @@ struct lb_batch_t {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int grid = 0;
+    int ty = 4, tz = 16;        // tile rows and chunk planes of every job (fixed at creation)
     bool own_stream = false;
 };
 
@@ -280,12 +281,12 @@ float batch_scale(const lb_batch_t* b, const lb_params& p) {
     return b->storage == LB_STORE_F16 ? std::ldexp(1.0f, p.scale_log2 ? p.scale_log2 : 16) : 1.0f;
 }
 
-FusedShape job_shape(int storage, const lb_params& p) {
+FusedShape job_shape(const lb_batch_t* b, const lb_params& p) {
     FusedShape fs;
-    fs.TY = batch_rows(storage);
+    fs.TY = b->ty;
     fs.tiles_x = (p.nx + kBatchTX - 1) / kBatchTX;
     fs.tiles_y = (p.ny + fs.TY - 1) / fs.TY;
-    fs.TZ = std::min(p.nz, 16);
+    fs.TZ = std::min(p.nz, b->tz);
     fs.chunks = (p.nz + fs.TZ - 1) / fs.TZ;
     fs.nblocks = fs.tiles_x * fs.tiles_y * fs.chunks;
     return fs;
@@ -358,11 +359,11 @@ int upload_items(lb_batch_t* b) {
 template <typename R, typename S>
 int launch_batch_step(lb_batch_t* b) {
     const float sc = b->storage == LB_STORE_F16 ? std::ldexp(1.0f, 16) : 1.0f;
-    hipLaunchKernelGGL((batch_phase_kernel<R, S>), dim3(b->grid), dim3(kBatchThreads), batch_phase_lds(b->storage),
+    hipLaunchKernelGGL((batch_phase_kernel<R, S>), dim3(b->grid), dim3(kBatchThreads), batch_phase_lds(b->storage, b->ty),
                        b->stream, (const BatchJob<R>*)b->d_jobs, b->d_items, b->d_nitems, b->d_gstep, sc);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return bfail(LB_EDEVICE, std::string("batch_phase_kernel: ") + hipGetErrorString(e));
-    hipLaunchKernelGGL((batch_collide_kernel<R, S>), dim3(b->grid), dim3(kBatchThreads), batch_collide_lds(b->storage),
+    hipLaunchKernelGGL((batch_collide_kernel<R, S>), dim3(b->grid), dim3(kBatchThreads), batch_collide_lds(b->storage, b->ty),
                        b->stream, (const BatchJob<R>*)b->d_jobs, b->d_items, b->d_nitems, b->d_gstep, sc);
     e = hipGetLastError();
     if (e != hipSuccess) return bfail(LB_EDEVICE, std::string("batch_collide_kernel: ") + hipGetErrorString(e));
@@ -481,6 +482,12 @@ int lb_batch_create(int32_t max_jobs, int64_t arena_bytes, int32_t storage, int3
     (void)hipGetDevice(&dev);
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
     b->grid = cus * 4;
+    // tile shape: the process setting (lb_set_tiles) or the default; rows halved
+    // until both passes fit the 64 KB of LDS a kernel gets without opting in
+    const TileSetting ts = tile_setting(TILE_BATCH, storage);
+    b->ty = ts.ty > 0 ? ts.ty : batch_rows(storage);
+    while (b->ty > 1 && batch_collide_lds(storage, b->ty) > 65536) b->ty /= 2;
+    b->tz = ts.tz > 0 ? ts.tz : 16;
     int rc = LB_OK;
     if ((rc = bcheck(hipMalloc((void**)&b->arena_base, (size_t)arena_bytes), "hipMalloc arena")) ||
         (rc = bcheck(hipMalloc(&b->d_jobs, desc_size(storage) * max_jobs), "hipMalloc job table")) ||
@@ -552,7 +559,7 @@ static int batch_admit(lb_batch_t* b, const lb_params* params, int64_t steps, in
     h.bytes = bytes;
     h.cd = make_coeffs<double>(h.p);
     h.cf = make_coeffs<float>(h.p);
-    h.fs = job_shape(b->storage, h.p);
+    h.fs = job_shape(b, h.p);
     char* b0 = b->arena_base + off;
     char* b1 = b0 + job_half(b->storage, N);
     const bool split = b->storage >= LB_STORE_F16;

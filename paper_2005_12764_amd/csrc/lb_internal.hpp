@@ -38,7 +38,13 @@ size_t pop_bytes(int storage, size_t N);
 
 // Tile kernels: 64-wide tiles of TY rows marching z-chunks of TZ planes.
 constexpr int kTX = 64;
-enum TileKind { TILE_COLLIDE = 0, TILE_SINGLE = 1, TILE_PHASE = 2 };
+enum TileKind { TILE_COLLIDE = 0, TILE_SINGLE = 1, TILE_PHASE = 2, TILE_BATCH = 3 };
+// Tile shape set through lb_set_tiles for (kind, storage): 0 = unset.
+struct TileSetting {
+    int ty, tz;
+};
+TileSetting tile_setting(int kind, int storage);
+void set_tile_setting(int kind, int storage, int ty, int tz);
 int env_int(const char* name, int dflt);
 int tile_halo(const lb_params& p);
 size_t tile_lds(const lb_params& p, int kind, int TY);

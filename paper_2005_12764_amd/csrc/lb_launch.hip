@@ -229,6 +229,16 @@ int env_int(const char* name, int dflt) {
     return (e && *e) ? std::atoi(e) : dflt;
 }
 
+namespace {
+TileSetting g_tiles[4][4] = {};  // [kind][storage]
+}  // namespace
+
+TileSetting tile_setting(int kind, int storage) {
+    if (kind < 0 || kind > 3 || storage < 0 || storage > 3) return TileSetting{0, 0};
+    return g_tiles[kind][storage];
+}
+void set_tile_setting(int kind, int storage, int ty, int tz) { g_tiles[kind][storage] = TileSetting{ty, tz}; }
+
 int tile_halo(const lb_params& p) { return 1 + ((p.nc_strength > 0.0) ? p.nc_range : 0); }
 
 size_t tile_lds(const lb_params& p, int kind, int TY) {
@@ -252,14 +262,16 @@ int tile_rows(const lb_params& p, int kind) {
     if (kind == TILE_SINGLE) {
         // 8 rows for raw storage; 16-bit storage takes 4 (its record ring makes
         // 8 rows a one-workgroup-per-CU tile)
-        const int want = env_int("LB_SINGLE_TY", split_storage(p) ? kSingleTYSmall : kSingleTY);
+        const int set = tile_setting(TILE_SINGLE, p.storage).ty;
+        const int want = set > 0 ? set : env_int("LB_SINGLE_TY", split_storage(p) ? kSingleTYSmall : kSingleTY);
         for (int ty : {want, kSingleTYSmall})
             if ((ty == kSingleTY || ty == kSingleTYSmall) && tile_lds(p, kind, ty) <= (size_t)device_lds_bytes())
                 return ty;
         return 0;
     }
     const char* env = kind == TILE_PHASE ? "LB_PHASE_TY" : "LB_COLLIDE_TY";
-    int want = env_int(env, 0);
+    int want = tile_setting(kind, p.storage).ty;
+    if (want <= 0) want = env_int(env, 0);
     if (want <= 0) {
         if (kind == TILE_PHASE) want = 8;
         else if (split_storage(p)) want = kind == TILE_COLLIDE ? 4 : 8;
@@ -276,7 +288,8 @@ FusedShape tile_shape(const lb_params& p, int kind, int target_blocks) {
     fs.tiles_x = (p.nx + kTX - 1) / kTX;
     fs.tiles_y = (p.ny + fs.TY - 1) / fs.TY;
     const int tiles = fs.tiles_x * fs.tiles_y;
-    int tz = env_int(kind == TILE_PHASE ? "LB_PHASE_TZ" : "LB_TZ", 0);
+    int tz = tile_setting(kind, p.storage).tz;
+    if (tz <= 0) tz = env_int(kind == TILE_PHASE ? "LB_PHASE_TZ" : "LB_TZ", 0);
     if (tz <= 0) {
         // aim for target_blocks workgroups, keeping chunks a few halos deep
         const int H = kind == TILE_PHASE ? 1 : tile_halo(p);

@@ -100,6 +100,7 @@ def lib():
         "lb_step": ([vp, i32], i32),
         "lb_moments": ([vp, vp, vp, vp, i32, i32, dp], i32),
         "lb_korteweg": ([vp, ctypes.c_double, i32, vp, vp, i32, i32, i32], i32),
+        "lb_set_tiles": ([i32, i32, i32, i32], i32),
         "lb_step_timed": ([vp, i32, dp], i32),
         "lb_get_state": ([vp, vp, i32, i32], i32),
         "lb_set_state": ([vp, vp, i32, i32], i32),
@@ -240,6 +241,14 @@ def lb_moments(h, rho_r=None, rho_b=None, mom=None, want_totals: bool = False):
         t = np.array(tot[:], dtype=np.float64).reshape(7, 2)
         return t
     return None
+
+
+TILES_PHASE, TILES_COLLIDE, TILES_ONE_READ, TILES_BATCH = 0, 1, 2, 3
+
+
+def lb_set_tiles(kind: int, storage: int, ty: int = 0, tz: int = 0) -> None:
+    """Tile rows / chunk planes of one tile kind for one storage (0 = default)."""
+    _check(lib().lb_set_tiles(int(kind), int(storage), int(ty), int(tz)))
 
 
 def lb_korteweg(h, lam: float, b: int, k_blocks=None, phi_blocks=None, accumulate: bool = False) -> None:
