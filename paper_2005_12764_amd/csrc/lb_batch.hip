@@ -263,7 +263,7 @@ struct lb_batch_t {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int grid = 0;
-    int ty = 4, tz = 16;        // tile rows and chunk planes of every job (fixed at creation)
+    int ty = 4, tz = 32;        // tile rows and chunk planes of every job (fixed at creation)
     bool own_stream = false;
 };
 
@@ -487,7 +487,7 @@ int lb_batch_create(int32_t max_jobs, int64_t arena_bytes, int32_t storage, int3
     const TileSetting ts = tile_setting(TILE_BATCH, storage);
     b->ty = ts.ty > 0 ? ts.ty : batch_rows(storage);
     while (b->ty > 1 && batch_collide_lds(storage, b->ty) > 65536) b->ty /= 2;
-    b->tz = ts.tz > 0 ? ts.tz : 16;
+    b->tz = ts.tz > 0 ? ts.tz : 32;
     int rc = LB_OK;
     if ((rc = bcheck(hipMalloc((void**)&b->arena_base, (size_t)arena_bytes), "hipMalloc arena")) ||
         (rc = bcheck(hipMalloc(&b->d_jobs, desc_size(storage) * max_jobs), "hipMalloc job table")) ||

@@ -273,7 +273,8 @@ int tile_rows(const lb_params& p, int kind) {
     int want = tile_setting(kind, p.storage).ty;
     if (want <= 0) want = env_int(env, 0);
     if (want <= 0) {
-        if (kind == TILE_PHASE) want = 8;
+        // the autotuner's choices for the 256^3 emulsion on MI355X
+        if (kind == TILE_PHASE) want = 4;
         else if (split_storage(p)) want = kind == TILE_COLLIDE ? 4 : 8;
         else want = p.storage == LB_STORE_F64 ? 8 : 4;
     }
@@ -290,6 +291,9 @@ FusedShape tile_shape(const lb_params& p, int kind, int target_blocks) {
     const int tiles = fs.tiles_x * fs.tiles_y;
     int tz = tile_setting(kind, p.storage).tz;
     if (tz <= 0) tz = env_int(kind == TILE_PHASE ? "LB_PHASE_TZ" : "LB_TZ", 0);
+    // the autotuner's choices for the 256^3 emulsion on MI355X: 16-plane chunks
+    // for the 16-bit phase pass and the raw-storage two-pass collide
+    if (tz <= 0 && (kind == TILE_PHASE || (kind == TILE_COLLIDE && !split_storage(p)))) tz = 16;
     if (tz <= 0) {
         // aim for target_blocks workgroups, keeping chunks a few halos deep
         const int H = kind == TILE_PHASE ? 1 : tile_halo(p);
