@@ -77,7 +77,7 @@ extern "C" {
 /* Tile kinds of lb_set_tiles. */
 #define LB_TILES_PHASE 0    /* phase-field pass of two-pass steps (16-bit storage) */
 #define LB_TILES_COLLIDE 1  /* collide-and-stream pass of two-pass steps */
-#define LB_TILES_ONE_READ 2 /* one-read step (rows 4 or 8) */
+#define LB_TILES_ONE_READ 2 /* one-read step (rows 4, 8 or 16) */
 #define LB_TILES_BATCH 3    /* both passes of the batched step (rows 1, 2, 4 or 8) */
 
 /* Element type of caller fields. */

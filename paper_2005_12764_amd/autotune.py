@@ -32,7 +32,7 @@ STORAGE_NAME = {W.F64: "f64", W.F32: "f32", W.F16: "f16", W.BF16: "bf16"}
 
 # candidate (rows, planes); planes 0 = the library's choice for the lattice
 CANDIDATES: Dict[int, List[Tuple[int, int]]] = {
-    lb.TILES_ONE_READ: [(ty, tz) for ty in (4, 8) for tz in (0, 16, 32, 64)],
+    lb.TILES_ONE_READ: [(ty, tz) for ty in (4, 8, 16) for tz in (0, 16, 32, 64)],
     lb.TILES_COLLIDE: [(ty, tz) for ty in (2, 4, 8) for tz in (0, 16, 32, 64)],
     lb.TILES_PHASE: [(ty, tz) for ty in (4, 8, 16) for tz in (0, 16, 32, 64)],
     lb.TILES_BATCH: [(ty, tz) for ty in (2, 4, 8) for tz in (8, 16, 32)],

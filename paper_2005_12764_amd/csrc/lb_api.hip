@@ -195,7 +195,7 @@ int lb_set_tiles(int32_t kind, int32_t storage, int32_t ty, int32_t tz) {
     static const int kind_of[4] = {TILE_PHASE, TILE_COLLIDE, TILE_SINGLE, TILE_BATCH};
     if (kind < LB_TILES_PHASE || kind > LB_TILES_BATCH) return fail(LB_EINVAL, "unknown tile kind");
     if (storage < LB_STORE_F64 || storage > LB_STORE_BF16) return fail(LB_EINVAL, "unknown storage");
-    const bool rows_ok = kind == LB_TILES_ONE_READ ? (ty == 0 || ty == 4 || ty == 8)
+    const bool rows_ok = kind == LB_TILES_ONE_READ ? (ty == 0 || ty == 4 || ty == 8 || ty == 16)
                                                    : (ty == 0 || ty == 1 || ty == 2 || ty == 4 || ty == 8 || ty == 16);
     if (!rows_ok || (kind == LB_TILES_BATCH && ty == 16)) return fail(LB_EINVAL, "tile rows not supported for this kind");
     if (tz < 0 || tz > 4096) return fail(LB_EINVAL, "tile planes outside 0..4096");

@@ -170,6 +170,7 @@ int single_pass(const LatticeView& v, const Src& src, const Dst& dst, const Coef
     int rc;
     if (fs.TY == kSingleTY) rc = single_ty<R, Src, Dst, kSingleTY>(v, src, dst, c, fs, t);
     else if (fs.TY == kSingleTYSmall) rc = single_ty<R, Src, Dst, kSingleTYSmall>(v, src, dst, c, fs, t);
+    else if (fs.TY == kSingleTYLarge) rc = single_ty<R, Src, Dst, kSingleTYLarge>(v, src, dst, c, fs, t);
     else return set_error(LB_EINVAL, "one-read tile does not fit in LDS");
     if (rc) return rc;
     if (t) (void)hipEventRecord(t->ev[2], v.stream);
@@ -260,12 +261,19 @@ size_t tile_lds(const lb_params& p, int kind, int TY) {
 // largest that keeps the LDS rings within the per-workgroup budget.
 int tile_rows(const lb_params& p, int kind) {
     if (kind == TILE_SINGLE) {
-        // 8 rows for raw storage; 16-bit storage takes 4 (its record ring makes
-        // 8 rows a one-workgroup-per-CU tile)
+        // FP32 lattices of 2^23 sites or more take 16 rows (the autotuner's choice
+        // at 256^3; smaller ones would leave CUs without a 1024-thread tile),
+        // other raw storage 8; 16-bit storage takes 4 (its record ring makes 8
+        // rows a one-workgroup-per-CU tile)
         const int set = tile_setting(TILE_SINGLE, p.storage).ty;
-        const int want = set > 0 ? set : env_int("LB_SINGLE_TY", split_storage(p) ? kSingleTYSmall : kSingleTY);
-        for (int ty : {want, kSingleTYSmall})
-            if ((ty == kSingleTY || ty == kSingleTYSmall) && tile_lds(p, kind, ty) <= (size_t)device_lds_bytes())
+        const size_t sites = (size_t)p.nx * p.ny * p.nz;
+        const int dflt = split_storage(p) ? kSingleTYSmall
+                         : (p.storage == LB_STORE_F32 && sites >= ((size_t)1 << 23)) ? kSingleTYLarge
+                                                                                    : kSingleTY;
+        const int want = set > 0 ? set : env_int("LB_SINGLE_TY", dflt);
+        for (int ty : {want, kSingleTY, kSingleTYSmall})
+            if ((ty == kSingleTY || ty == kSingleTYSmall || ty == kSingleTYLarge) &&
+                tile_lds(p, kind, ty) <= (size_t)device_lds_bytes())
                 return ty;
         return 0;
     }
@@ -294,6 +302,8 @@ FusedShape tile_shape(const lb_params& p, int kind, int target_blocks) {
     // the autotuner's choices for the 256^3 emulsion on MI355X: 16-plane chunks
     // for the 16-bit phase pass and the raw-storage two-pass collide
     if (tz <= 0 && (kind == TILE_PHASE || (kind == TILE_COLLIDE && !split_storage(p)))) tz = 16;
+    // 16-row one-read tiles are 1024-thread workgroups, one per CU: aim for 256
+    if (kind == TILE_SINGLE && fs.TY == kSingleTYLarge) target_blocks = 256;
     if (tz <= 0) {
         // aim for target_blocks workgroups, keeping chunks a few halos deep
         const int H = kind == TILE_PHASE ? 1 : tile_halo(p);
@@ -433,6 +443,7 @@ int launch_korteweg(const LatticeView& v, double lam, int b, void* kout, void* p
         if (v.part_valid && v.part_in) {
             const FusedShape fs = tile_shape(*v.p, TILE_SINGLE);
             if (fs.TY == kSingleTY) rc = assemble_phase<R, S, kSingleTY>(v, src, fs);
+            else if (fs.TY == kSingleTYLarge) rc = assemble_phase<R, S, kSingleTYLarge>(v, src, fs);
             else rc = assemble_phase<R, S, kSingleTYSmall>(v, src, fs);
             field = phi_of<kTX>((Part2<R>*)v.part_in, v.g);
         } else {

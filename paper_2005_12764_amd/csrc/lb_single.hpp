@@ -83,9 +83,11 @@ __host__ __device__ constexpr int dir_of(int cx, int cy, int cz) {
 }
 
 // Rows of the one-read tile (one site per thread and plane): 8, or 4 when
-// the LDS of 8 rows exceeds the workgroup's budget (FP64 with a wide halo).
+// the LDS of 8 rows exceeds the workgroup's budget (FP64 with a wide halo),
+// or 16 (a 1024-thread workgroup, one per CU) when chosen by tile setting.
 constexpr int kSingleTY = 8;
 constexpr int kSingleTYSmall = 4;
+constexpr int kSingleTYLarge = 16;
 
 // Own box of a site: its tile column [x0, x1) x [y0, y1) and z chunk [z0, z1).
 struct OwnBox {

@@ -40,7 +40,7 @@ def test_set_tiles_validates_its_arguments():
     lb.lb_set_tiles(lb.TILES_COLLIDE, W.F32, 8, 32)
     lb.lb_set_tiles(lb.TILES_COLLIDE, W.F32, 0, 0)
     for args in [(4, W.F32, 4, 0), (lb.TILES_COLLIDE, 7, 4, 0), (lb.TILES_COLLIDE, W.F32, 3, 0),
-                 (lb.TILES_ONE_READ, W.F32, 2, 0), (lb.TILES_BATCH, W.F16, 16, 0),
+                 (lb.TILES_ONE_READ, W.F32, 2, 0), (lb.TILES_ONE_READ, W.F32, 1, 0), (lb.TILES_BATCH, W.F16, 16, 0),
                  (lb.TILES_PHASE, W.F16, 8, -1), (lb.TILES_PHASE, W.F16, 8, 5000)]:
         with pytest.raises(lb.LbError):
             lb.lb_set_tiles(*args)

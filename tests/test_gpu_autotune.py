@@ -49,6 +49,26 @@ def test_one_read_survives_a_change_of_tiles(tiles):
     assert state_errors(got, ref)["worst"] < 1e-13
 
 
+def test_one_read_with_sixteen_rows(tiles):
+    # 1024-thread tiles: agree with the two-pass step to FP32 rounding and
+    # resume from a checkpoint bit for bit
+    w = W.two_droplets(n=(70, 40, 19), R=6, gap=2.0, A=0.01, nc_strength=0.03, nc_range=2)
+    w.params["bc"] = (0, 1, 0)
+    ref = _run(w, W.F32, lb.KERNEL_TWOPASS, 30)
+    tiles(lb.TILES_ONE_READ, W.F32, 16, 0)
+    p = dict(w.params, storage=W.F32, kernel=lb.KERNEL_FUSED)
+    with lb.Lattice(p) as A, lb.Lattice(p) as B:
+        A.init(w.rho_r, w.rho_b).step(12)
+        ck = A.save_raw()
+        A.step(18)
+        straight = A.state()
+        B.init(w.rho_r, w.rho_b).step(1)
+        B.load_raw(ck)
+        B.step(18)
+        assert np.array_equal(B.state(), straight)
+    assert state_errors(straight, ref)["worst"] < 2e-6
+
+
 def test_batch_results_do_not_depend_on_tiles(tiles):
     jobs = [W.periodic_emulsion(seed=k, n=s) for k, s in enumerate((32, 48))]
 
