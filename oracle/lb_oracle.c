@@ -49,7 +49,9 @@
  *   10 nc_strength, 11 nc_range K, 12 nc_hmin, 13..15 body force density,
  *   16 eps_g (|G| below which n = 0), 17 g_iface (interface threshold of the
  *   near-contact probe), 18..35 wall velocities of the six faces in the order
- *   -x, +x, -y, +y, -z, +z (3 components each; used on wall axes only).
+ *   -x, +x, -y, +y, -z, +z (3 components each; used on wall axes only),
+ *   36 interface model (0 colour gradient, 1 Shan-Chen), 37 G_C (Shan-Chen
+ *   coupling).
  *
  * Moving walls (the sheared channel of Sec. 5 has walls sliding at +-U): a
  * population reflected by a wall face moving with velocity U gains
@@ -101,6 +103,8 @@ typedef struct {
     double eps_g, g_iface;
     double uwall[6][3];
     int moving;
+    int model;      /* 0 colour gradient, 1 Shan-Chen */
+    double g_sc;    /* Shan-Chen coupling G_C */
 } prm_t;
 
 static prm_t unpack(const double *p) {
@@ -125,6 +129,8 @@ static prm_t unpack(const double *p) {
             q.uwall[f][a] = p[18 + 3 * f + a];
             if (q.uwall[f][a] != 0.0 && q.bc[f / 2]) q.moving = 1;
         }
+    q.model = (int)p[36];
+    q.g_sc = p[37];
     return q;
 }
 
@@ -395,9 +401,79 @@ void orc_nearcontact(const double *p, const double *G, double *Fnc) {
     }
 }
 
+/* ------------------------------------------------------------------ */
+/* Shan-Chen interface model (Sec. 2.1, "Multi-component flows").       */
+/* ------------------------------------------------------------------ */
+
+/* Inter-component force densities of eq. shanchen_force,
+ *   F^r(x) = -G_C rho_r(x) sum_i w_i rho_b(x + c_i) c_i,
+ *   F^b(x) = -G_C rho_b(x) sum_i w_i rho_r(x + c_i) c_i.
+ * The paper states that positive G_C repels; its printed formula has no
+ * minus sign, which would make positive G_C attract, so the sign is taken
+ * from the statement (the usual Shan-Chen form).  A neighbour beyond a
+ * halfway wall is its mirror image, as for the colour gradient.
+ * rho_r, rho_b: N values; Fr, Fb: [3][N]. */
+void orc_sc_force(const double *p, const double *rho_r, const double *rho_b, double *Fr, double *Fb) {
+    init_tables();
+    prm_t q = unpack(p);
+    size_t N = nsites(&q);
+#pragma omp parallel for schedule(static)
+    for (long long s = 0; s < (long long)N; ++s) {
+        int x, y, z;
+        coords(&q, (size_t)s, &x, &y, &z);
+        double sb[3] = {0.0, 0.0, 0.0}, sr[3] = {0.0, 0.0, 0.0};
+        for (int i = 1; i < Q; ++i) {
+            int xn = stencil_coord(x + CV[i][0], q.n[0], q.bc[0]);
+            int yn = stencil_coord(y + CV[i][1], q.n[1], q.bc[1]);
+            int zn = stencil_coord(z + CV[i][2], q.n[2], q.bc[2]);
+            size_t t = sidx(&q, xn, yn, zn);
+            for (int a = 0; a < 3; ++a) {
+                sb[a] += W[i] * rho_b[t] * CV[i][a];
+                sr[a] += W[i] * rho_r[t] * CV[i][a];
+            }
+        }
+        for (int a = 0; a < 3; ++a) {
+            Fr[(size_t)a * N + s] = -q.g_sc * rho_r[s] * sb[a];
+            Fb[(size_t)a * N + s] = -q.g_sc * rho_b[s] * sr[a];
+        }
+    }
+}
+
+/* Local collision of one site in the Shan-Chen model: both components relax
+ * with the mixture rate toward f^eq(rho_k, u), u = j/rho (Sec. 2.1,
+ * eq:twobgk), each with its own exact-difference source
+ * f^eq(rho_k, u + F^k/rho_k) - f^eq(rho_k, u) (eq:edm), where F^k is the
+ * component's Shan-Chen force plus its share (rho_k/rho) of the body force.
+ * No perturbation and no recolouring: the force alone keeps the components
+ * apart.  A component absent from the site (rho_k = 0) has a zero source. */
+void orc_sc_collide_site(const double *p, const double *fr, const double *fb, const double *Fr,
+                         const double *Fb, double *out_r, double *out_b) {
+    init_tables();
+    prm_t q = unpack(p);
+    double rho_r = 0.0, rho_b = 0.0, j[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < Q; ++i) {
+        rho_r += fr[i];
+        rho_b += fb[i];
+        for (int a = 0; a < 3; ++a) j[a] += (fr[i] + fb[i]) * CV[i][a];
+    }
+    double rho = rho_r + rho_b;
+    double u[3], dur[3], dub[3];
+    for (int a = 0; a < 3; ++a) {
+        u[a] = j[a] / rho;
+        double Fkr = Fr[a] + (rho_r / rho) * q.force[a];
+        double Fkb = Fb[a] + (rho_b / rho) * q.force[a];
+        dur[a] = rho_r > 0.0 ? Fkr / rho_r : 0.0;
+        dub[a] = rho_b > 0.0 ? Fkb / rho_b : 0.0;
+    }
+    double omega = orc_omega(q.tau_r, q.tau_b, rho_r, rho_b);
+    orc_bgk_edm(omega, rho_r, u, dur, fr, out_r);
+    orc_bgk_edm(omega, rho_b, u, dub, fb, out_b);
+}
+
 /* Collision of the whole lattice: f (post-streaming) -> fpost (post-collision,
  * pre-streaming).  Optional outputs of the intermediate fields (NULL = skip):
- * phi[N], G[3N], Fnc[3N]. */
+ * phi[N], G[3N], Fnc[3N]; in the Shan-Chen model G receives F^r and Fnc
+ * receives F^b. */
 void orc_collide(const double *p, const double *f, double *fpost, double *phi_out,
                  double *G_out, double *Fnc_out) {
     init_tables();
@@ -412,6 +488,29 @@ void orc_collide(const double *p, const double *f, double *fpost, double *phi_ou
     /* 1. moments and the phase field phi = (rho_r - rho_b)/rho */
     orc_moments(p, f, rr, rb, NULL);
     for (size_t s = 0; s < N; ++s) phi[s] = (rr[s] - rb[s]) / (rr[s] + rb[s]);
+    if (q.model == 1) {
+        /* Shan-Chen: forces from the component densities, then the local
+         * collision; G_out and Fnc_out receive F^r and F^b */
+        orc_sc_force(p, rr, rb, G, Fnc);
+#pragma omp parallel for schedule(static)
+        for (long long s = 0; s < (long long)N; ++s) {
+            double fr[Q], fb[Q], orr[Q], ob[Q], Fr[3], Fb[3];
+            for (int i = 0; i < Q; ++i) {
+                fr[i] = f[(size_t)i * N + s];
+                fb[i] = f[(size_t)(Q + i) * N + s];
+            }
+            for (int a = 0; a < 3; ++a) {
+                Fr[a] = G[(size_t)a * N + s];
+                Fb[a] = Fnc[(size_t)a * N + s];
+            }
+            orc_sc_collide_site(p, fr, fb, Fr, Fb, orr, ob);
+            for (int i = 0; i < Q; ++i) {
+                fpost[(size_t)i * N + s] = orr[i];
+                fpost[(size_t)(Q + i) * N + s] = ob[i];
+            }
+        }
+        goto done;
+    }
     /* 2. colour gradient */
     orc_phase_gradient(p, phi, G);
     /* 3. near-contact force */
@@ -434,6 +533,7 @@ void orc_collide(const double *p, const double *f, double *fpost, double *phi_ou
             fpost[(size_t)(Q + i) * N + s] = ob[i];
         }
     }
+done:
     if (phi_out) memcpy(phi_out, phi, N * sizeof(double));
     if (G_out) memcpy(G_out, G, 3 * N * sizeof(double));
     if (Fnc_out) memcpy(Fnc_out, Fnc, 3 * N * sizeof(double));

@@ -64,6 +64,8 @@ def lib():
         L.orc_nc_amplitude.restype = ctypes.c_double
         L.orc_nearcontact.argtypes = [dp, dp, dp]
         L.orc_collide.argtypes = [dp, dp, dp, dp, dp, dp]
+        L.orc_sc_force.argtypes = [dp, dp, dp, dp, dp]
+        L.orc_sc_collide_site.argtypes = [dp, dp, dp, dp, dp, dp, dp]
         L.orc_stream.argtypes = [dp, dp, dp]
         L.orc_step.argtypes = [dp, dp, dp, ctypes.c_int]
         L.orc_phase_field.argtypes = [dp, dp, dp]
@@ -104,6 +106,8 @@ class Params:
     eps_g: float = 1e-12
     g_iface: float = 0.05
     wall_velocity: tuple = ((0.0, 0.0, 0.0),) * 6   # faces -x, +x, -y, +y, -z, +z
+    model: int = 0                 # interface model: 0 colour gradient, 1 Shan-Chen
+    g_sc: float = 0.0              # Shan-Chen coupling G_C (> 0 repulsive)
 
     @property
     def shape(self):
@@ -113,7 +117,8 @@ class Params:
         return np.array([self.nx, self.ny, self.nz, *self.bc, self.tau_r, self.tau_b,
                          self.A, self.beta, self.nc_strength, self.nc_range, self.nc_hmin,
                          *self.body_force, self.eps_g, self.g_iface,
-                         *np.asarray(self.wall_velocity, dtype=np.float64).reshape(18)],
+                         *np.asarray(self.wall_velocity, dtype=np.float64).reshape(18),
+                         self.model, self.g_sc],
                         dtype=np.float64)
 
 
@@ -220,7 +225,25 @@ def nearcontact(prm: Params, G):
     return F
 
 
+def sc_force(prm: Params, rho_r, rho_b):
+    """Shan-Chen force densities (F^r, F^b), each (3, nz, ny, nx)."""
+    Fr = np.zeros((3,) + prm.shape)
+    Fb = np.zeros((3,) + prm.shape)
+    lib().orc_sc_force(_p(prm.vec()), _p(_f64(rho_r)), _p(_f64(rho_b)), _p(Fr), _p(Fb))
+    return Fr, Fb
+
+
+def sc_collide_site(prm: Params, fr, fb, Fr, Fb):
+    outr, outb = np.zeros(Q), np.zeros(Q)
+    lib().orc_sc_collide_site(_p(prm.vec()), _p(_f64(fr)), _p(_f64(fb)), _p(_f64(Fr)),
+                              _p(_f64(Fb)), _p(outr), _p(outb))
+    return outr, outb
+
+
 def collide(prm: Params, f, want_fields: bool = False):
+    """Collision of the whole lattice.  With want_fields, also the phase
+    field, the colour gradient G and the near-contact force (Shan-Chen model:
+    F^r and F^b in place of G and the near-contact force)."""
     post = np.zeros_like(_f64(f))
     if want_fields:
         phi = np.zeros(prm.shape)

@@ -17,7 +17,8 @@ def oracle_params(p: dict, eps_g=None, g_iface=0.05) -> O.Params:
                     nc_strength=p["nc_strength"], nc_range=p["nc_range"],
                     nc_hmin=p["nc_hmin"], body_force=tuple(p["body_force"]),
                     eps_g=eps_g, g_iface=g_iface,
-                    wall_velocity=tuple(map(tuple, p.get("wall_velocity", ((0.0, 0.0, 0.0),) * 6))))
+                    wall_velocity=tuple(map(tuple, p.get("wall_velocity", ((0.0, 0.0, 0.0),) * 6))),
+                    model=int(p.get("model", 0)), g_sc=float(p.get("g_sc", 0.0)))
 
 
 def rel_l2(a, b):
