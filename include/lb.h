@@ -243,8 +243,10 @@ int lb_batch_create(int32_t max_jobs, int64_t arena_bytes, int32_t storage, int3
 /* Admit one job that will run `steps` steps: validates params (storage must
  * equal the batch's; near-contact range at most 2), places it in the arena,
  * writes its initial state f^eq(rho_k, u) (a 16-bit job also takes its first
- * step here, from the raw FP32 initial state).  *slot gets its slot index.
- * LB_ENOMEM when no slot or arena space is free.  Synchronises the stream. */
+ * step here, from the raw FP32 initial state, so 16-bit jobs need steps >= 1;
+ * each keeps its own deviation scale 2^scale_log2).  *slot gets its slot index.
+ * LB_EINVAL for invalid parameters or a 16-bit job with steps = 0; LB_ENOMEM
+ * when no slot or arena space is free.  Synchronises the stream. */
 int lb_batch_add(lb_batch_t* b, const lb_params* params, const void* rho_r, const void* rho_b,
                  const void* u, int32_t dtype, int32_t on_device, int64_t steps, int32_t* slot);
 

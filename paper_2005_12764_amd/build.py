@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liblb.so")
 
-SOURCES = ["lb_api.hip", "lb_launch.hip", "lb_batch.hip"]
+SOURCES = ["lb_api.hip", "lb_launch.hip", "lb_lean.hip", "lb_batch.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -22,14 +22,33 @@ HIPCC_FLAGS = [
 
 
 def build(verbose: bool = False) -> str:
-    """Compile every HIP source of the library into liblb.so (always rebuilds)."""
+    """Compile every HIP source of the library into liblb.so (always rebuilds;
+    the translation units compile in parallel, then link)."""
+    from concurrent.futures import ThreadPoolExecutor
+
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    jobs = []
+    for s in SOURCES:
+        obj = os.path.join(objdir, os.path.splitext(s)[0] + ".o")
+        jobs.append((obj, [hipcc, *HIPCC_FLAGS, "-c", "-I", INCLUDE, "-I", CSRC, "-o", obj,
+                           os.path.join(CSRC, s)]))
+
+    def run(job):
+        obj, cmd = job
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        return obj
+
+    with ThreadPoolExecutor(max_workers=len(jobs)) as ex:
+        objs = list(ex.map(run, jobs))
     tmp = LIB + ".tmp"
-    cmd = [hipcc, *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC, "-o", tmp, *srcs]
+    link = [hipcc, *HIPCC_FLAGS, "-o", tmp, *objs]
     if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
+        print(" ".join(link), flush=True)
+    subprocess.run(link, check=True)
     os.replace(tmp, LIB)
     return LIB
 

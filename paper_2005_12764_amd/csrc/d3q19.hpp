@@ -48,14 +48,34 @@ __host__ __device__ constexpr R inv_clen(int i) {
 template <typename R>
 struct Coeffs {
     R inv_nu_r, inv_nu_b;  // 1 / nu_k, nu_k = (tau_k - 1/2)/3
+    R omega;               // the mixture rate when tau_r == tau_b (then 1/tau at every site)
     R half_A;              // A/2 of the perturbation
     R beta;
-    R eps_g;               // |G| at or below which n = 0
-    R g_iface;             // interface threshold of the near-contact probe
+    R eps_g, eps_g2;       // |G| at or below which n = 0, and its square
+    R g_iface, g_iface2;   // interface threshold of the near-contact probe, and its square
     R nc_strength, nc_hmin;
     R fx, fy, fz;          // body force density
     int nc_range;          // 0 = near-contact off
+    int same_tau;          // tau_r == tau_b: omega above holds everywhere
 };
+
+// Reciprocal and reciprocal square root.  FP32: the hardware estimates
+// (v_rcp_f32, v_rsq_f32, within 1 ulp), used where an FP32 result only feeds
+// further rounding-level arithmetic; FP64: correctly rounded.
+__device__ __forceinline__ float rcp_of(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp_of(double x) { return 1.0 / x; }
+__device__ __forceinline__ float rsq_of(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsq_of(double x) { return 1.0 / sqrt(x); }
+
+// Is |G| (G with squared length g2) above the threshold e (squared e2)?
+// FP32 compares squares; FP64 compares the root, as the definition reads.
+__device__ __forceinline__ bool above(float g2, float e, float e2) { (void)e; return g2 > e2; }
+__device__ __forceinline__ bool above(double g2, double e, double e2) { (void)e2; return sqrt(g2) > e; }
+__device__ __forceinline__ bool at_least(float g2, float e, float e2) { (void)e; return g2 >= e2; }
+__device__ __forceinline__ bool at_least(double g2, double e, double e2) { (void)e2; return sqrt(g2) >= e; }
+// 1/|G| for a G known to be non-zero.
+__device__ __forceinline__ float inv_norm(float g2) { return rsq_of(g2); }
+__device__ __forceinline__ double inv_norm(double g2) { return 1.0 / sqrt(g2); }
 
 // Outputs of one site's collision that the 16-bit storage keeps per site.
 template <typename R>
@@ -90,10 +110,11 @@ __device__ __forceinline__ void collide(R (&t)[Q], R (&d)[Q], R gx, R gy, R gz, 
     const R rho = R(1) + drho;            // sum of the weights is 1
     // The colour split uses rc = sum_i (w_i + t_i), rounded term by term as
     // the colour difference is: a pure component (d_i = +-(w_i + t_i)) then
-    // gives phi = +-1 and rho_b or rho_r = 0 exactly, and stays pure.
-    const R rr = R(0.5) * (rc + dif), rb = R(0.5) * (rc - dif);
-    const R inv_rc = R(1) / rc;
-    const R inv_rho = R(1) / rho;
+    // gives phi = +-1 exactly (a divided, not multiplied, quotient) and
+    // x_r, x_b = 1, 0 exactly, and stays pure.
+    const R phi = dif / rc;               // x_r - x_b
+    const R xr = R(0.5) + R(0.5) * phi, xb = R(0.5) - R(0.5) * phi;
+    const R inv_rho = rcp_of(rho);
     const R ux = jx * inv_rho, uy = jy * inv_rho, uz = jz * inv_rho;
     // exact-difference velocity shift du = F^k/rho_k with F^k = (rho_k/rho) F
     const R dx = Fx * inv_rho, dy = Fy * inv_rho, dz = Fz * inv_rho;
@@ -102,21 +123,22 @@ __device__ __forceinline__ void collide(R (&t)[Q], R (&d)[Q], R gx, R gy, R gz, 
     // - 1.5 du.s], without subtracting two equilibria
     const R sx = ux + vx, sy = uy + vy, sz = uz + vz;
     const R ds = dx * sx + dy * sy + dz * sz;
-    // divided, not multiplied by 1/rc, so that x_r, phi are exactly 1 there
-    const R xr = rr / rc, xb = rb / rc;
-    const R phi = dif / rc;               // x_r - x_b
     // mixture relaxation: 1/nu_bar = x_r/nu_r + x_b/nu_b, w = 2 cs2/(2 nu_bar + cs2)
-    const R nubar = R(1) / (xr * c.inv_nu_r + xb * c.inv_nu_b);
-    const R omega = R(2) / (R(6) * nubar + R(1));
+    R omega = c.omega;
+    if (!c.same_tau) {
+        const R nubar = rcp_of(xr * c.inv_nu_r + xb * c.inv_nu_b);
+        omega = R(2) * rcp_of(R(6) * nubar + R(1));
+    }
     const R uu = ux * ux + uy * uy + uz * uz;
 
     const R g2 = gx * gx + gy * gy + gz * gz;
-    const R gm = sqrt(g2);
-    const bool has_n = gm > c.eps_g;
-    const R inv_gm = has_n ? R(1) / gm : R(0);
-    // perturbation amplitude (A/2)|G| and recolouring strength beta rho_r rho_b / rho
-    const R pa = has_n ? c.half_A * gm : R(0);
-    const R seg = has_n ? c.beta * rr * rb * inv_rc : R(0);
+    const bool has_n = above(g2, c.eps_g, c.eps_g2);
+    const R inv_gm = has_n ? inv_norm(g2) : R(0);
+    const R gm = g2 * inv_gm;
+    // perturbation amplitude (A/2)|G| and recolouring strength
+    // beta rho_r rho_b / rho = beta x_r x_b rc
+    const R pa = c.half_A * gm;
+    const R seg = has_n ? c.beta * xr * xb * rc : R(0);
     const R nx = gx * inv_gm, ny = gy * inv_gm, nz = gz * inv_gm;
 
 #pragma unroll

@@ -66,10 +66,16 @@ Coeffs<R> make_coeffs(const lb_params& p) {
     const double nu_r = (p.tau_r - 0.5) / 3.0, nu_b = (p.tau_b - 0.5) / 3.0;
     c.inv_nu_r = R(1.0 / nu_r);
     c.inv_nu_b = R(1.0 / nu_b);
+    c.same_tau = p.tau_r == p.tau_b;
+    c.omega = R(1.0 / p.tau_r);  // 2 cs2 / (2 nu + cs2) = 1/tau
     c.half_A = R(0.5 * p.A);
     c.beta = R(p.beta);
-    c.eps_g = R(p.eps_g > 0 ? p.eps_g : (p.storage == LB_STORE_F64 ? 1e-12 : 1e-6));
-    c.g_iface = R(p.g_iface > 0 ? p.g_iface : 0.05);
+    const double eps = p.eps_g > 0 ? p.eps_g : (p.storage == LB_STORE_F64 ? 1e-12 : 1e-6);
+    const double gi = p.g_iface > 0 ? p.g_iface : 0.05;
+    c.eps_g = R(eps);
+    c.eps_g2 = R(eps * eps);
+    c.g_iface = R(gi);
+    c.g_iface2 = R(gi * gi);
     c.nc_strength = R(p.nc_strength);
     c.nc_hmin = R(p.nc_hmin);
     c.fx = R(p.body_force[0]);

@@ -44,7 +44,7 @@ struct BatchJob {
     int active;
     int tiles;              // tiles_x * tiles_y
     int fresh;              // the step at `first` reads an initial (not collided) state
-    int pad;
+    float scale;            // 16-bit deviation scale 2^scale_log2 of this job (1 otherwise)
 };
 
 struct WorkItem {
@@ -107,7 +107,7 @@ __device__ __forceinline__ void item_tile(const BatchJob<R>& J, const WorkItem& 
 template <typename R, typename S>
 __global__ __launch_bounds__(kBatchThreads, Occupancy<S>::waves) void batch_phase_kernel(
     const BatchJob<R>* __restrict__ jobs, const WorkItem* __restrict__ items, const int* __restrict__ n_items,
-    const long long* __restrict__ gstep, float scale) {
+    const long long* __restrict__ gstep) {
     extern __shared__ unsigned char lds_raw[];
     const int n = *n_items;
     const long long gs = *gstep;
@@ -116,7 +116,7 @@ __global__ __launch_bounds__(kBatchThreads, Occupancy<S>::waves) void batch_phas
         const BatchJob<R>& J = jobs[it.slot];
         if (!J.active || gs < J.first || gs >= J.last) continue;  // uniform over the workgroup
         const int par = (int)((gs - J.first) & 1);
-        const S src = storage_view<S>(J.buf[par], (size_t)J.g.N, scale);
+        const S src = storage_view<S>(J.buf[par], (size_t)J.g.N, J.scale);
         int x0, y0, za, zb;
         item_tile(J, it, x0, y0, za, zb);
         RecRing<kBatchTX> rr{reinterpret_cast<f4*>(lds_raw), J.fs.TY + 2};
@@ -129,7 +129,7 @@ __global__ __launch_bounds__(kBatchThreads, Occupancy<S>::waves) void batch_phas
 template <typename R, typename S>
 __global__ __launch_bounds__(kBatchThreads, Occupancy<S>::waves) void batch_collide_kernel(
     const BatchJob<R>* __restrict__ jobs, const WorkItem* __restrict__ items, const int* __restrict__ n_items,
-    const long long* __restrict__ gstep, float scale) {
+    const long long* __restrict__ gstep) {
     extern __shared__ unsigned char lds_raw[];
     const int n = *n_items;
     const long long gs = *gstep;
@@ -138,8 +138,8 @@ __global__ __launch_bounds__(kBatchThreads, Occupancy<S>::waves) void batch_coll
         const BatchJob<R>& J = jobs[it.slot];
         if (!J.active || gs < J.first || gs >= J.last) continue;  // uniform over the workgroup
         const int par = (int)((gs - J.first) & 1);
-        const S src = storage_view<S>(J.buf[par], (size_t)J.g.N, scale);
-        const S dst = storage_view<S>(J.buf[par ^ 1], (size_t)J.g.N, scale);
+        const S src = storage_view<S>(J.buf[par], (size_t)J.g.N, J.scale);
+        const S dst = storage_view<S>(J.buf[par ^ 1], (size_t)J.g.N, J.scale);
         int x0, y0, za, zb;
         item_tile(J, it, x0, y0, za, zb);
         PhiRing<R, kBatchTX, kBatchH> ring{reinterpret_cast<R*>(lds_raw), J.fs.TY + 2 * kBatchH};
@@ -310,6 +310,7 @@ void fill_desc(const lb_batch_t* b, const HostJob& h, BatchJob<R>& d) {
     d.active = h.used ? 1 : 0;
     d.tiles = h.fs.tiles_x * h.fs.tiles_y;
     d.fresh = h.fresh ? 1 : 0;
+    d.scale = batch_scale(b, h.p);
 }
 
 size_t desc_size(int storage) { return storage == LB_STORE_F64 ? sizeof(BatchJob<double>) : sizeof(BatchJob<float>); }
@@ -358,13 +359,12 @@ int upload_items(lb_batch_t* b) {
 
 template <typename R, typename S>
 int launch_batch_step(lb_batch_t* b) {
-    const float sc = b->storage == LB_STORE_F16 ? std::ldexp(1.0f, 16) : 1.0f;
     hipLaunchKernelGGL((batch_phase_kernel<R, S>), dim3(b->grid), dim3(kBatchThreads), batch_phase_lds(b->storage, b->ty),
-                       b->stream, (const BatchJob<R>*)b->d_jobs, b->d_items, b->d_nitems, b->d_gstep, sc);
+                       b->stream, (const BatchJob<R>*)b->d_jobs, b->d_items, b->d_nitems, b->d_gstep);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return bfail(LB_EDEVICE, std::string("batch_phase_kernel: ") + hipGetErrorString(e));
     hipLaunchKernelGGL((batch_collide_kernel<R, S>), dim3(b->grid), dim3(kBatchThreads), batch_collide_lds(b->storage, b->ty),
-                       b->stream, (const BatchJob<R>*)b->d_jobs, b->d_items, b->d_nitems, b->d_gstep, sc);
+                       b->stream, (const BatchJob<R>*)b->d_jobs, b->d_items, b->d_nitems, b->d_gstep);
     e = hipGetLastError();
     if (e != hipSuccess) return bfail(LB_EDEVICE, std::string("batch_collide_kernel: ") + hipGetErrorString(e));
     hipLaunchKernelGGL(batch_tick_kernel, dim3(1), dim3(64), 0, b->stream, b->d_gstep);
@@ -539,6 +539,10 @@ static int batch_admit(lb_batch_t* b, const lb_params* params, int64_t steps, in
     if (K + 1 > kBatchH) return bfail(LB_EINVAL, "batched jobs support near-contact ranges up to 2");
     if (make_geom(*params).moving) return bfail(LB_EINVAL, "batched jobs do not support moving walls");
     if (steps < 0) return bfail(LB_EINVAL, "steps must be >= 0");
+    // a 16-bit job's raw FP32 initial state lives in the shared staging area
+    // only until its first step (taken here) encodes it into its own buffers
+    if (b->storage >= LB_STORE_F16 && steps == 0)
+        return bfail(LB_EINVAL, "16-bit batched jobs need steps >= 1");
     int s = -1;
     for (int k = 0; k < b->max_jobs; ++k)
         if (!b->jobs[k].used) {

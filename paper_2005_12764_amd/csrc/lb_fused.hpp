@@ -76,15 +76,8 @@ __device__ __forceinline__ void load_rec_plane(const Geom& g, const Src& src, co
         const size_t s = (size_t)site_of(g, xx, yy, zz);
         const f4 a = *reinterpret_cast<const f4*>(src.rec + 8 * s);
         const f4 b = *reinterpret_cast<const f4*>(src.rec + 8 * s + 4);
-#if LB_RING_SOA
-        float* pf = reinterpret_cast<float*>(dstp);
-        const int stride = rr.LY * LX;
-        pf[k] = a.x; pf[stride + k] = a.y; pf[2 * stride + k] = a.z; pf[3 * stride + k] = a.w;
-        pf[4 * stride + k] = b.x; pf[5 * stride + k] = b.y; pf[6 * stride + k] = b.z; pf[7 * stride + k] = b.w;
-#else
         dstp[2 * k] = a;
         dstp[2 * k + 1] = b;
-#endif
     }
 }
 
@@ -118,9 +111,10 @@ __device__ __forceinline__ void ring_near_contact(const Geom& g, const PhiRing<R
                                                   int y, int z, int ly, int lx, R gx, R gy, R gz,
                                                   const Coeffs<R>& c, R& Fx, R& Fy, R& Fz) {
     constexpr int NP = 2 * H + 1;
-    const R gm = sqrt(gx * gx + gy * gy + gz * gz);
-    if (!(gm >= c.g_iface)) return;
-    const R nx = -gx / gm, ny = -gy / gm, nz = -gz / gm;
+    const R g2 = gx * gx + gy * gy + gz * gz;
+    if (!at_least(g2, c.g_iface, c.g_iface2)) return;
+    const R inv_gm = inv_norm(g2);
+    const R nx = -gx * inv_gm, ny = -gy * inv_gm, nz = -gz * inv_gm;
     int h = 0;
     for (int k = 1; k <= c.nc_range && k < H; ++k) {
         const int ox = (int)round(R(k) * nx);
@@ -133,9 +127,9 @@ __device__ __forceinline__ void ring_near_contact(const Geom& g, const PhiRing<R
         const int t0 = (s0 + oz + NP) % NP;
         R qx, qy, qz;
         lds_gradient<R, TX, H>(ring, (t0 + NP - 1) % NP, t0, (t0 + 1) % NP, ly + oy, lx + ox, qx, qy, qz);
-        const R qm = sqrt(qx * qx + qy * qy + qz * qz);
+        const R q2 = qx * qx + qy * qy + qz * qz;
         const R dot = qx * gx + qy * gy + qz * gz;
-        if (qm >= c.g_iface && dot < R(0)) {
+        if (dot < R(0) && at_least(q2, c.g_iface, c.g_iface2)) {
             h = k;
             break;
         }
@@ -159,8 +153,6 @@ __device__ __forceinline__ void fused_tile(const Geom& g, const Src& src, const 
     const int LY = ring.LY;
     const int tid = threadIdx.x;
     const int nt = blockDim.x;
-    Src srcr = src;
-    if constexpr (Src::ring) srcr.ring_plane_floats = rr.LY * RecRing<TX>::LX * 8;
     for (int p = za - H; p < zb + H; ++p) {
         const int slot = (p - (za - H)) % NP;
         // ---- phase field of plane p on the tile and its halo
@@ -194,7 +186,7 @@ __device__ __forceinline__ void fused_tile(const Geom& g, const Src& src, const 
                 if constexpr (Src::ring) {
                     const f4* const planes[3] = {rr.plane((cz - za) % 3), rr.plane((cz - za + 1) % 3),
                                                  rr.plane((cz - za + 2) % 3)};
-                    srcr.pull_ring(g, s, x, y, cz, t, d, planes, ty + 1, tx + 1, RecRing<TX>::LX);
+                    src.pull_ring(g, s, x, y, cz, t, d, planes, ty + 1, tx + 1, RecRing<TX>::LX);
                 } else {
                     src.pull(g, s, x, y, cz, t, d);
                 }
@@ -222,8 +214,6 @@ __device__ __forceinline__ void phase_tile(const Geom& g, const Src& src, R* __r
     const int tid = threadIdx.x;
     const int nt = blockDim.x;
     if constexpr (Src::ring) {
-        Src srcr = src;
-        srcr.ring_plane_floats = rr.LY * RecRing<TX>::LX * 8;
         for (int q = za - 1; q <= zb; ++q) {
             load_rec_plane<Src, TX>(g, src, rr, (q - za + 1) % 3, x0, y0, q);
             __syncthreads();
@@ -237,7 +227,7 @@ __device__ __forceinline__ void phase_tile(const Geom& g, const Src& src, R* __r
                     if (x >= g.nx || y >= g.ny) continue;
                     const int s = site_of(g, x, y, cz);
                     R t[Q], d[Q];
-                    srcr.pull_ring(g, s, x, y, cz, t, d, planes, ty + 1, tx + 1, RecRing<TX>::LX);
+                    src.pull_ring(g, s, x, y, cz, t, d, planes, ty + 1, tx + 1, RecRing<TX>::LX);
                     phi[s] = phase_of(t, d);
                 }
             }

@@ -59,6 +59,10 @@ struct StepEvents {
     hipEvent_t ev[3];
 };
 int launch_step(const LatticeView& v, int kernel, const StepEvents* t = nullptr);
+// Tile kernel of the one-read step for raw storage (lb_lean.hip): collide and
+// stream fin into fout, gathering the next state's own phase sums.
+template <typename T>
+int launch_lean(const LatticeView& v, const T* fin, T* fout, const Coeffs<T>& c, const FusedShape& fs);
 int launch_init(const LatticeView& v, const void* rr, const void* rb, const void* u, int dtype);
 int launch_import(const LatticeView& v, const void* f, int dtype);
 int launch_export(const LatticeView& v, void* out, int dtype);

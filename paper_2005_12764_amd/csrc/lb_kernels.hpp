@@ -111,12 +111,13 @@ __device__ __forceinline__ int nbr_source(const Geom& g, const Nbr& n, int i, in
     return bb ? n.s : src;
 }
 
-// Moving-wall term of direction i arriving at (x,y,z) by reflection:
-// 2 w_i (c_i . U)/c_s^2 summed over the wall faces the upstream site x - c_i
-// lies beyond (reference density 1).
-__device__ __forceinline__ double wall_term(const Geom& g, int i, int x, int y, int z) {
+// Moving-wall term of direction i arriving at (x,y,z) by reflection, in the
+// compute type: 2 w_i (c_i . U)/c_s^2 summed over the wall faces the upstream
+// site x - c_i lies beyond (reference density 1).
+template <typename R>
+__device__ __forceinline__ R wall_term(const Geom& g, int i, int x, int y, int z) {
     using L = Lattice;
-    double cu = 0.0;
+    R cu = R(0);
     const int v[3] = {x - L::cx[i], y - L::cy[i], z - L::cz[i]};
     const int n[3] = {g.nx, g.ny, g.nz};
     const int w[3] = {g.wx, g.wy, g.wz};
@@ -124,9 +125,9 @@ __device__ __forceinline__ double wall_term(const Geom& g, int i, int x, int y, 
     for (int a = 0; a < 3; ++a) {
         if (!w[a] || (v[a] >= 0 && v[a] < n[a])) continue;
         const double* U = g.uw[2 * a + (v[a] < 0 ? 0 : 1)];
-        cu += L::cx[i] * U[0] + L::cy[i] * U[1] + L::cz[i] * U[2];
+        cu += R(L::cx[i]) * R(U[0]) + R(L::cy[i]) * R(U[1]) + R(L::cz[i]) * R(U[2]);
     }
-    return 6.0 * weight<double>(i) * cu;
+    return R(6) * weight<R>(i) * cu;
 }
 
 // ---------------------------------------------------------------------------
@@ -185,7 +186,7 @@ struct RawPop {
                 }
                 have = true;
             }
-            const R add = R(wall_term(g, i, x, y, z));
+            const R add = wall_term<R>(g, i, x, y, z);
             t[i] += add;
             d[i] += add * (sd / st);   // add x_r - add x_b
         }
@@ -229,10 +230,6 @@ struct Half<__hip_bfloat16> {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-#ifndef LB_RING_SOA
-#define LB_RING_SOA 0
-#endif
-
 // c_d . a for d = i (sg = 1) or its opposite (sg = -1), summed x, y, z from
 // the non-zero components only, so that a value and its reflected reading
 // round identically.
@@ -259,7 +256,6 @@ struct SplitPop {
     H* dev;
     size_t N;
     float scale, inv_scale;
-    int ring_plane_floats;  // floats per record-ring plane (for the SoA ring layout)
 
     // Equilibrium excess of direction i (read as d = i, sg = 1, or as its
     // opposite after a bounce-back, sg = -1) from the source record ra:
@@ -327,7 +323,7 @@ struct SplitPop {
             int dir;
             (void)pull_source(g, i, x, y, z, s, dir);
             if (dir == i) continue;
-            const R add = R(wall_term(g, i, x, y, z));
+            const R add = wall_term<R>(g, i, x, y, z);
             t[i] += add;
             d[i] += add * (R(2) * R(xr) - R(1));
         }
@@ -350,23 +346,10 @@ struct SplitPop {
             const bool bb = (d != i);
             const f4* pl = bb ? ring[1] : ring[1 - L::cz[i]];
             const int pos = bb ? (ly * LXR + lx) : ((ly - L::cy[i]) * LXR + lx - L::cx[i]);
-#if LB_RING_SOA
-            // ring plane = 8 float arrays of LY*LXR entries (plane stride passed via LXR * LYR)
-            const float* pf = reinterpret_cast<const float*>(pl);
-            const int stride = ring_plane_floats / 8;
-            const f4 ra = {pf[pos], pf[stride + pos], pf[2 * stride + pos], pf[3 * stride + pos]};
-            const f4 rb = {pf[4 * stride + pos], pf[5 * stride + pos], pf[6 * stride + pos], pf[7 * stride + pos]};
-            decode<R>(i, d, ra, rb, dev[(size_t)d * N + src], t[i], d_[i]);
-#else
             decode<R>(i, d, pl[2 * pos], pl[2 * pos + 1], dev[(size_t)d * N + src], t[i], d_[i]);
-#endif
         }
         if constexpr (MW) {
-#if LB_RING_SOA
-            const float xr_own = reinterpret_cast<const float*>(ring[1])[4 * (ring_plane_floats / 8) + ly * LXR + lx];
-#else
             const float xr_own = ring[1][2 * (ly * LXR + lx) + 1].x;
-#endif
             if (g.moving) add_wall_terms<R>(g, s, x, y, z, xr_own, t, d_);
         }
     }
@@ -463,9 +446,10 @@ template <typename R>
 __device__ __forceinline__ void near_contact(const Geom& g, const R* __restrict__ phi, int x, int y,
                                              int z, R gx, R gy, R gz, const Coeffs<R>& c, R& Fx,
                                              R& Fy, R& Fz) {
-    const R gm = sqrt(gx * gx + gy * gy + gz * gz);
-    if (!(gm >= c.g_iface)) return;
-    const R nx = -gx / gm, ny = -gy / gm, nz = -gz / gm;
+    const R g2 = gx * gx + gy * gy + gz * gz;
+    if (!at_least(g2, c.g_iface, c.g_iface2)) return;
+    const R inv_gm = inv_norm(g2);
+    const R nx = -gx * inv_gm, ny = -gy * inv_gm, nz = -gz * inv_gm;
     int h = 0;
     for (int k = 1; k <= c.nc_range; ++k) {
         int px = x + (int)round(R(k) * nx);
@@ -476,9 +460,9 @@ __device__ __forceinline__ void near_contact(const Geom& g, const R* __restrict_
         if (g.wz) { if (pz < 0 || pz >= g.nz) break; } else pz = wrap_any(pz, g.nz);
         R qx, qy, qz;
         gradient<R>(g, phi, px, py, pz, qx, qy, qz);
-        const R qm = sqrt(qx * qx + qy * qy + qz * qz);
+        const R q2 = qx * qx + qy * qy + qz * qz;
         const R dot = qx * gx + qy * gy + qz * gz;
-        if (qm >= c.g_iface && dot < R(0)) {
+        if (dot < R(0) && at_least(q2, c.g_iface, c.g_iface2)) {
             h = k;
             break;
         }

@@ -9,6 +9,7 @@
 
 #include "lb_internal.hpp"
 #include "lb_korteweg.hpp"
+#include "lb_lean.hpp"
 #include "lb_single.hpp"
 
 namespace lbm {
@@ -118,16 +119,22 @@ int zmarch(const LatticeView& v, const Src& src, const Dst& dst, const Coeffs<R>
 // streams and gathers the next state's sums and interior phi.
 template <typename R, typename Src, typename Dst, int TY, int H>
 int single_h(const LatticeView& v, const Src& src, const Dst& dst, const Coeffs<R>& c, const FusedShape& fs) {
-    const size_t lds = tile_lds(*v.p, TILE_SINGLE, TY);
-    auto kern = single_kernel<R, Src, Dst, kTX, TY, H>;
-    if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return set_error(LB_EDEVICE, (std::string("single_kernel LDS: ") + hipGetErrorString(e)).c_str());
+    if constexpr (!Src::ring && !Dst::ring) {
+        // raw storage: the lean tile kernel
+        return launch_lean<R>(v, src.f, dst.f, c, fs);
+    } else {
+        const size_t lds = tile_lds(*v.p, TILE_SINGLE, TY);
+        auto kern = single_kernel<R, Src, Dst, kTX, TY, H>;
+        if (lds > 65536) {
+            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess)
+                return set_error(LB_EDEVICE, (std::string("single_kernel LDS: ") + hipGetErrorString(e)).c_str());
+        }
+        hipLaunchKernelGGL(kern, dim3(fs.nblocks), dim3(kTX * TY), lds, v.stream, v.g, src, dst, c, fs,
+                           (const Part2<R>*)v.part_in, (Part2<R>*)v.part_out);
+        return launch_status("single_kernel");
     }
-    hipLaunchKernelGGL(kern, dim3(fs.nblocks), dim3(kTX * TY), lds, v.stream, v.g, src, dst, c, fs,
-                       (const Part2<R>*)v.part_in, (Part2<R>*)v.part_out);
-    return launch_status("single_kernel");
 }
 
 // phi of the face sites of a one-read state (its interior phi is already in
@@ -203,7 +210,7 @@ int two_pass(const LatticeView& v, const Src& src, const Dst& dst, const Coeffs<
     int rc = phase_pass<R>(v, src);
     if (rc) return rc;
     if (t) (void)hipEventRecord(t->ev[1], v.stream);
-    if (tile_rows(*v.p, TILE_COLLIDE) > 0 && env_int("LB_TWOPASS_SIMPLE", 0) == 0) {
+    if (tile_rows(*v.p, TILE_COLLIDE) > 0) {
         rc = zmarch<R>(v, src, dst, c, (const R*)v.phi);
     } else {
         hipLaunchKernelGGL((collide_kernel<R, Src, Dst>), dim3(grid_for(v.g.N)), dim3(kBlock), 0, v.stream, v.g, src,
@@ -250,9 +257,11 @@ size_t tile_lds(const lb_params& p, int kind, int TY) {
     switch (kind) {
         case TILE_PHASE: return rec;
         case TILE_COLLIDE: return ((phi + 15) & ~size_t(15)) + (split ? rec : 0);
-        default:  // TILE_SINGLE: phi ring, record ring, exchange of the c_y != 0 directions,
-                  // running x-face sums of the edge lanes
-            return ((phi + 15) & ~size_t(15)) + (split ? rec : 0) + (size_t)2 * kXchDirs * kTX * TY * real_size(p) +
+        default:  // TILE_SINGLE: phi ring, record ring, exchange of the c_y != 0 directions
+                  // (raw storage: rows padded by a zero at both ends), running x-face sums
+                  // of the edge lanes
+            return ((phi + 15) & ~size_t(15)) + (split ? rec : 0) +
+                   (size_t)2 * kXchDirs * (split ? kTX : kTX + 2) * TY * real_size(p) +
                    (size_t)2 * 3 * TY * 2 * real_size(p);
     }
 }
@@ -334,7 +343,9 @@ int choose_kernel(const lb_params& p) {
     bool moving = false;
     for (int f = 0; f < 6; ++f)
         for (int k = 0; k < 3; ++k) moving |= p.bc[f / 2] != 0 && p.wall_velocity[f][k] != 0.0;
-    if (split_storage(p) || moving || !fits) return LB_KERNEL_TWOPASS;
+    // (the one-read step's 32-bit byte offsets need 10 x sites x value size < 2^32)
+    const bool small = (uint64_t)kResArrays * real_size(p) * (uint64_t)p.nx * p.ny * p.nz < ((uint64_t)1 << 32);
+    if (split_storage(p) || moving || !fits || !small) return LB_KERNEL_TWOPASS;
     return LB_KERNEL_FUSED;
 }
 

@@ -1,0 +1,457 @@
+// lb_lean.hpp -- the one-read step for raw (FP64/FP32) storage, written for
+// the CDNA4 instruction mix.
+//
+// Same step and same phase-sum bookkeeping as single_tile (lb_single.hpp):
+// the tile collides and streams its sites and gathers, in the same fixed
+// order, the own phase sums of the next state.  What differs is how the work
+// maps onto a wavefront:
+//   - a tile row is one wavefront, so the row's y and the plane's z are
+//     wave-uniform: every upstream row offset (periodic wrap, wall tests) is
+//     scalar arithmetic, and each of the 38 pulls and 38 stores is a global
+//     access with a scalar row base plus one of three loop-invariant per-lane
+//     column offsets (x, x-1, x+1 with the periodic wrap);
+//   - the phase-field ring is staged row by row with scalar row addresses;
+//   - neighbours in the same row are read with DPP wavefront shifts that fill
+//     the lane beyond the row's end with zero, so a source outside the tile
+//     (or beyond an x wall) contributes nothing without a per-lane test, and
+//     the shift folds into the add that consumes it;
+//   - values for other rows go through LDS rows padded with a zero at both
+//     ends, for the same reason;
+//   - every lane runs the collision (lanes beyond the lattice on clamped
+//     coordinates); only stores are masked.
+// The kernel the step launched before (single_kernel) computes the same
+// quantities; the two agree to rounding (the collision is shared).
+#pragma once
+#include "lb_single.hpp"
+
+namespace lbm {
+
+__device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// The 2 Q population arrays of a buffer as four buffer resources of up to
+// ten arrays each: a pull or store is then one buffer access with the row in
+// a scalar offset and the column in a per-lane offset, with no 64-bit address
+// arithmetic per access.  Each range is exact, so an access outside it reads
+// zero or is dropped.  Needs 10 N sizeof(T) < 2^32 (checked on the host).
+constexpr int kResArrays = 10;
+constexpr unsigned kRsrcWord3 = 0x00020000;  // raw 32-bit buffer on gfx9-family targets
+template <typename T>
+struct PopRes {
+    __amdgpu_buffer_rsrc_t r[4];
+    __device__ __forceinline__ PopRes(const T* f, unsigned N) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const unsigned na = (unsigned)min(kResArrays, 2 * Q - k * kResArrays);
+            r[k] = __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(f) + (size_t)k * kResArrays * N, 0,
+                                                     (int)(na * N * (unsigned)sizeof(T)), (int)kRsrcWord3);
+        }
+    }
+};
+__device__ __forceinline__ float res_load(float, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+__device__ __forceinline__ double res_load(double, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+// non-temporal store (aux = 2: nt)
+__device__ __forceinline__ void res_store(float v, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 2);
+}
+__device__ __forceinline__ void res_store(double v, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, voff, soff, 2);
+}
+
+// Value of lane l-1 of the wavefront (0 in lane 0) and of lane l+1 (0 in
+// lane 63): DPP wave_shr:1 / wave_shl:1 with out-of-range lanes reading zero.
+__device__ __forceinline__ float from_left(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float from_right(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, true));
+}
+__device__ __forceinline__ double from_left(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), 0x138, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x138, 0xf, 0xf, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double from_right(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), 0x130, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x130, 0xf, 0xf, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Exchange rows in LDS: per tile row, kXchDirs x 2 values (w_i + t_i, d_i)
+// of the directions with c_y != 0, each a row of 64 lanes with a zero pad
+// before and after it.
+constexpr int kLeanRowPad = kTX + 2;
+template <typename R, int TY>
+__host__ __device__ constexpr size_t lean_xch_bytes() {
+    return (size_t)TY * 2 * kXchDirs * kLeanRowPad * sizeof(R);
+}
+
+// Upstream row (scalar): element offset (z*ny + y)*nx of the row a population
+// with velocity (., cy, cz) arriving in row (y, z) comes from, with the
+// periodic wrap.  W: the lattice may have walls; `bb` is then set when that
+// row lies beyond one (the population is a bounce-back).
+template <bool W>
+__device__ __forceinline__ unsigned upstream_row(const Geom& g, int y, int z, int cy, int cz, bool& bb) {
+    int ys = y - cy, zs = z - cz;
+    const bool out_y = ys < 0 || ys >= g.ny, out_z = zs < 0 || zs >= g.nz;
+    ys = ys < 0 ? ys + g.ny : (ys >= g.ny ? ys - g.ny : ys);
+    zs = zs < 0 ? zs + g.nz : (zs >= g.nz ? zs - g.nz : zs);
+    bb = W && ((g.wy && out_y) || (g.wz && out_z));
+    return (unsigned)((zs * g.ny + ys) * g.nx);
+}
+
+// As xedge_rows, reading the exchange rows of the lean tile: the in-plane
+// terms from the rows above and below that the edge lanes of those rows send
+// across this x face (ascending direction); the chunk's last plane is then
+// complete.
+template <typename R, int TY, int SX>
+__device__ __forceinline__ void lean_xedge_rows(const Geom& g, const R* __restrict__ xch, Part2<R>* __restrict__ vs,
+                                                int ty, int tx, int nrows, int y, int cz, int za, int zb, int bd,
+                                                Part2<R>* __restrict__ xf) {
+    using L = Lattice;
+    constexpr int XROW = 2 * kXchDirs * kLeanRowPad;
+    constexpr int side = SX < 0 ? 0 : 1;
+    Part2<R>* v = vs + side * 3 * TY + ty;
+    Part2<R> P = v[((cz - za) % 3) * TY];
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        if (L::cx[i] != SX || L::cz[i] != 0 || L::cy[i] == 0) continue;
+        const int ys = ty - L::cy[i];
+        if (ys < 0 || ys >= nrows) continue;
+        const R* src = xch + ys * XROW + 1 + tx;
+        P.rc += src[(2 * xch_slot(i)) * kLeanRowPad];
+        P.dn += src[(2 * xch_slot(i) + 1) * kLeanRowPad];
+    }
+    if (cz == zb - 1) xf[xface_at(g, bd, 1 - side, y, cz)] = P;
+    else v[((cz - za) % 3) * TY] = P;
+}
+
+// One tile of the lean one-read step: columns [x0, x0+64) x [y0, y0+TY),
+// planes [za, zb); blockDim.x == 64 * TY.  W: the lattice has walls (an
+// all-periodic lattice carries none of their tests; the lanes next to an x
+// wall take their bounce-backs from a second, masked pull).
+template <typename R, typename T, int TY, int H, bool W>
+__device__ __forceinline__ void lean_tile(const Geom& g, const T* fin, T* fout,
+                                          const Coeffs<R>& c, R* __restrict__ ringb, R* __restrict__ xch,
+                                          Part2<R>* __restrict__ vs, int x0, int y0, int za, int zb,
+                                          const R* __restrict__ phi_in, Part2<R>* __restrict__ part_out,
+                                          R* __restrict__ phi_out) {
+    using L = Lattice;
+    constexpr int TX = kTX;
+    constexpr int LX = TX + 2 * H;
+    constexpr int NP = 2 * H + 1;
+    constexpr int LY = TY + 2 * H;
+    constexpr int PLANE = LY * LX;
+    constexpr int XROW = 2 * kXchDirs * kLeanRowPad;  // exchange reals per tile row
+    const unsigned N = (unsigned)g.N;  // 10 N sizeof(T) < 2^32 (checked on the host)
+    const int lane = threadIdx.x & 63;
+    const int ty = wave_uniform(threadIdx.x >> 6);
+    const int x = x0 + lane;
+    const int y = y0 + ty;
+    const int x1 = min(x0 + TX, g.nx), y1 = min(y0 + TY, g.ny);
+    const int nrows = y1 - y0;
+    const bool xin = x < g.nx;
+    const bool row_in = y < g.ny;
+    const bool ragged = x1 - x0 < TX;
+    // clamped coordinates: lanes and rows beyond the lattice compute on a
+    // valid site and store nothing
+    const int xc = xin ? x : g.nx - 1;
+    const int yc = row_in ? y : g.ny - 1;
+    // per-lane column offsets of the pulls: x, x - 1 and x + 1 with the wrap
+    // (beyond an x wall the lane's own column; its bounce-back is re-pulled)
+    const unsigned cx0 = (unsigned)xc;
+    const bool WX = W && g.wx;
+    const unsigned cxm = (unsigned)(xc == 0 ? (WX ? 0 : g.nx - 1) : xc - 1);
+    const unsigned cxp = (unsigned)(xc == g.nx - 1 ? (WX ? xc : 0) : xc + 1);
+    const bool wall_xlo = WX && xc == 0, wall_xhi = WX && xc == g.nx - 1;
+    // the same as 32-bit byte offsets: a scalar base plus one of these is a
+    // global access with an SGPR base (no 64-bit address arithmetic per access)
+    const unsigned bx0 = cx0 * (unsigned)sizeof(T), bxm = cxm * (unsigned)sizeof(T),
+                   bxp = cxp * (unsigned)sizeof(T);
+    // phase-ring columns of this lane: x0 - H + lane and x0 - H + 64 + lane
+    const int ra = halo_coord(x0 - H + lane, g.nx, g.wx);
+    const int rb = halo_coord(x0 - H + TX + lane, g.nx, g.wx);
+    // edge lanes of the row and the columns their x-face sums go to
+    Part2<R>* const xf = part_out + g.N;
+    int bd_lo = 0, bd_hi = 0;
+    const bool edge_lo = row_in && lane == 0 && xface_dest<TX>(g, x0, x1, -1, bd_lo);
+    const bool edge_hi = row_in && x == x1 - 1 && xface_dest<TX>(g, x0, x1, 1, bd_hi);
+    // zero pads of this row's exchange slots
+    R* const xrow = xch + ty * XROW;
+    if (lane < 2 * kXchDirs) {
+        xrow[lane * kLeanRowPad] = R(0);
+        xrow[lane * kLeanRowPad + kLeanRowPad - 1] = R(0);
+    }
+    R prev_dn = R(0), prev_rc = R(0), cur_dn = R(0), cur_rc = R(0);
+
+    // phase field of plane q on the tile and its halo, rows ty, ty + TY, ...:
+    // loaded into registers one plane ahead, so that the loads of plane p + 1
+    // are in flight while plane p is collided
+    constexpr int NR = (LY + TY - 1) / TY;
+    R pfa[NR], pfb[NR];
+    auto fetch = [&](int q) {
+        const int zz = halo_coord(q, g.nz, g.wz);
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            const int r = ty + k * TY;
+            if (r < LY) {
+                const int yy = halo_coord(y0 - H + r, g.ny, g.wy);
+                const R* rowp = phi_in + (size_t)(zz * g.ny + yy) * g.nx;
+                pfa[k] = rowp[ra];
+                pfb[k] = lane < 2 * H ? rowp[rb] : R(0);
+            }
+        }
+    };
+    fetch(za - H);
+
+    for (int p = za - H; p < zb + H; ++p) {
+        const int slot = (p - (za - H)) % NP;
+        // ---- phase field of plane p into its ring slot
+        {
+            R* dstp = ringb + slot * PLANE;
+#pragma unroll
+            for (int k = 0; k < NR; ++k) {
+                const int r = ty + k * TY;
+                if (r < LY) {
+                    dstp[r * LX + lane] = pfa[k];
+                    if (lane < 2 * H) dstp[r * LX + TX + lane] = pfb[k];
+                }
+            }
+        }
+        __syncthreads();
+        if (p + 1 < zb + H) fetch(p + 1);
+        const int cz = p - H;
+        if (cz < za) continue;  // uniform over the workgroup
+        const int s0 = (cz - (za - H)) % NP;
+        const int sm = (s0 + NP - 1) % NP, sp = (s0 + 1) % NP;
+        // N re-read each plane: the array offsets a N then stay scalar
+        // arithmetic inside the loop instead of loop-invariant scalar
+        // registers (which spill)
+        unsigned Np = N;
+        asm volatile("" : "+s"(Np));
+        // buffer resources rebuilt each plane (short-lived scalar registers)
+        const T* fin_p = fin;
+        T* fout_p = fout;
+        asm volatile("" : "+s"(fin_p), "+s"(fout_p));
+        const PopRes<T> fi(fin_p, Np), fo(fout_p, Np);
+        constexpr unsigned SZ = (unsigned)sizeof(T);
+        const unsigned own_row = (unsigned)((cz * g.ny + yc) * g.nx);
+        // byte offset of array a (0..2Q-1) at element e within its resource
+        auto soff = [&](int a, unsigned e) { return ((unsigned)(a % kResArrays) * Np + e) * SZ; };
+        // ---- pull (x, y, cz): row in the scalar offset, column per lane
+        R t[Q], d[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            bool bb;
+            const unsigned row = upstream_row<W>(g, yc, cz, L::cy[i], L::cz[i], bb);
+            const unsigned col = L::cx[i] > 0 ? bxm : (L::cx[i] < 0 ? bxp : bx0);
+            if (W && bb) {
+                // a bounce-back reads the site itself in the opposite direction
+                const int o = L::opp[i];
+                t[i] = res_load(R(0), fi.r[o / kResArrays], bx0, soff(o, own_row));
+                d[i] = res_load(R(0), fi.r[(Q + o) / kResArrays], bx0, soff(Q + o, own_row));
+            } else {
+                t[i] = res_load(R(0), fi.r[i / kResArrays], col, soff(i, row));
+                d[i] = res_load(R(0), fi.r[(Q + i) / kResArrays], col, soff(Q + i, row));
+            }
+        }
+        if constexpr (W) {
+            if (wall_xlo || wall_xhi) {
+#pragma unroll
+                for (int i = 1; i < Q; ++i) {
+                    if (!((L::cx[i] > 0 && wall_xlo) || (L::cx[i] < 0 && wall_xhi))) continue;
+                    const int o = L::opp[i];
+                    t[i] = res_load(R(0), fi.r[o / kResArrays], bx0, soff(o, own_row));
+                    d[i] = res_load(R(0), fi.r[(Q + o) / kResArrays], bx0, soff(Q + o, own_row));
+                }
+            }
+        }
+        // ---- colour gradient from the ring: base at (ty + H - 1, lane + H - 1)
+        R gx, gy, gz;
+        {
+            const int b = (ty + H - 1) * LX + lane + H - 1;
+            const R* pm = ringb + sm * PLANE + b;
+            const R* p0 = ringb + s0 * PLANE + b;
+            const R* pp = ringb + sp * PLANE + b;
+            R ax = R(0), ay = R(0), az = R(0);
+#pragma unroll
+            for (int i = 1; i < Q; ++i) {
+                const R* pl = L::cz[i] < 0 ? pm : (L::cz[i] > 0 ? pp : p0);
+                const R v = weight<R>(i) * pl[(1 + L::cy[i]) * LX + 1 + L::cx[i]];
+                if (L::cx[i]) ax += L::cx[i] > 0 ? v : -v;
+                if (L::cy[i]) ay += L::cy[i] > 0 ? v : -v;
+                if (L::cz[i]) az += L::cz[i] > 0 ? v : -v;
+            }
+            gx = R(3) * ax;
+            gy = R(3) * ay;
+            gz = R(3) * az;
+        }
+        R Fx = c.fx, Fy = c.fy, Fz = c.fz;
+        if (H > 1 && c.nc_range > 0) {
+            PhiRing<R, TX, H> ring{ringb, LY};
+            ring_near_contact<R, TX, H>(g, ring, s0, xc, yc, cz, ty + H, lane + H, gx, gy, gz, c, Fx, Fy, Fz);
+        }
+        collide<R>(t, d, gx, gy, gz, Fx, Fy, Fz, c, nullptr);
+        // ---- store (x, y, cz) and keep the values a later pull reads
+        if (row_in && xin) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                res_store(T(t[i]), fo.r[i / kResArrays], bx0, soff(i, own_row));
+                res_store(T(d[i]), fo.r[(Q + i) / kResArrays], bx0, soff(Q + i, own_row));
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            t[i] = R(T(t[i]));
+            d[i] = R(T(d[i]));
+        }
+        if (ragged) {
+            // lanes beyond the lattice hand nothing to their neighbours
+            if (!xin) {
+#pragma unroll
+                for (int i = 0; i < Q; ++i) {
+                    t[i] = -weight<R>(i);
+                    d[i] = R(0);
+                }
+            }
+        }
+        // bounce-backs into this site: its own values, before the in-plane group
+        {
+            const bool ylo = W && g.wy && yc == 0, yhi = W && g.wy && yc == g.ny - 1;
+            const bool zlo = W && g.wz && cz == 0, zhi = W && g.wz && cz == g.nz - 1;
+#pragma unroll
+            for (int i = 1; i < Q; ++i) {
+                const bool ryz = (L::cy[i] > 0 && ylo) || (L::cy[i] < 0 && yhi) || (L::cz[i] > 0 && zlo) ||
+                                 (L::cz[i] < 0 && zhi);
+                if constexpr (W) {
+                    const bool rx = (L::cx[i] > 0 && wall_xlo) || (L::cx[i] < 0 && wall_xhi);
+                    if (ryz || rx) {
+                        cur_rc += weight<R>(i) + t[L::opp[i]];
+                        cur_dn += d[L::opp[i]];
+                    }
+                } else {
+                    if (ryz) {
+                        cur_rc += weight<R>(i) + t[L::opp[i]];
+                        cur_dn += d[L::opp[i]];
+                    }
+                }
+            }
+        }
+        // ---- hand the stored values of the directions with c_y != 0 to the
+        // rows they stream to (LDS), w_i + t_i and d_i
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            if (L::cy[i] == 0) continue;
+            xrow[(2 * xch_slot(i)) * kLeanRowPad + 1 + lane] = weight<R>(i) + t[i];
+            xrow[(2 * xch_slot(i) + 1) * kLeanRowPad + 1 + lane] = d[i];
+        }
+        if (edge_lo) xedge_own<R, TY, -1>(g, t, d, vs, ty, y, cz, za, zb, bd_lo, xf);
+        if (edge_hi) xedge_own<R, TY, 1>(g, t, d, vs, ty, y, cz, za, zb, bd_hi, xf);
+        __syncthreads();
+        if (edge_lo) lean_xedge_rows<R, TY, -1>(g, xch, vs, ty, lane, nrows, y, cz, za, zb, bd_lo, xf);
+        if (edge_hi) lean_xedge_rows<R, TY, 1>(g, xch, vs, ty, lane, nrows, y, cz, za, zb, bd_hi, xf);
+        // value of direction i from the source (x - cx, y - cy) in plane cz:
+        // 0 when the source is outside the tile or beyond a wall
+        auto from = [&](int i, R& va, R& vd) {
+            if (L::cy[i] != 0) {
+                // (a source row beyond a y wall is also outside the tile's rows)
+                const int ys = ty - L::cy[i];
+                if (ys < 0 || ys >= nrows) {
+                    va = R(0);
+                    vd = R(0);
+                    return;
+                }
+                const R* src = xch + ys * XROW + lane + 1 - L::cx[i];
+                va = src[(2 * xch_slot(i)) * kLeanRowPad];
+                vd = src[(2 * xch_slot(i) + 1) * kLeanRowPad];
+            } else {
+                const R a = weight<R>(i) + t[i];
+                if (L::cx[i] > 0) {
+                    va = from_left(a);
+                    vd = from_left(d[i]);
+                } else if (L::cx[i] < 0) {
+                    va = from_right(a);
+                    vd = from_right(d[i]);
+                } else {
+                    va = a;
+                    vd = d[i];
+                }
+            }
+        };
+        // a site on an x or y face of the box keeps its own sums for the assembly
+        const bool face_xy =
+            lane == 0 || lane == TX - 1 || x == g.nx - 1 || ty == 0 || ty == TY - 1 || y == g.ny - 1;
+        const bool site_in = row_in && xin;
+        // destination cz - 1: sources in plane cz are its last group
+        if (cz - 1 >= za) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                if (L::cz[i] != -1) continue;
+                R va, vd;
+                from(i, va, vd);
+                prev_rc += va;
+                prev_dn += vd;
+            }
+            if (site_in) {
+                const size_t sm1 = (size_t)((cz - 1) * g.ny + y) * g.nx + x;
+                if (cz - 1 == za || face_xy) part_out[sm1] = Part2<R>{prev_dn, prev_rc};
+                else phi_out[sm1] = prev_dn / prev_rc;
+            }
+        }
+        // destination cz: in-plane sources
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            if (L::cz[i] != 0) continue;
+            R va, vd;
+            from(i, va, vd);
+            cur_rc += va;
+            cur_dn += vd;
+        }
+        // destination cz + 1: sources in plane cz are its first group
+        R next_dn = R(0), next_rc = R(0);
+        if (cz + 1 < zb) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                if (L::cz[i] != 1) continue;
+                R va, vd;
+                from(i, va, vd);
+                next_rc += va;
+                next_dn += vd;
+            }
+        }
+        prev_dn = cur_dn;
+        prev_rc = cur_rc;
+        cur_dn = next_dn;
+        cur_rc = next_rc;
+        // the chunk's last plane has no own sources above it
+        if (cz == zb - 1 && site_in) part_out[(size_t)(cz * g.ny + y) * g.nx + x] = Part2<R>{prev_dn, prev_rc};
+        // no barrier here: the next staging overwrites ring slots that only
+        // this plane's collide read, and every thread passed the barrier after
+        // that collide before it gathers; the exchange rows are next written
+        // after the next staging's barrier
+    }
+}
+
+template <typename R, typename T, int TY, int H, bool W>
+__global__ __launch_bounds__(kTX * TY) void lean_kernel(Geom g, const T* __restrict__ fin, T* __restrict__ fout,
+                                                       Coeffs<R> c, FusedShape fs,
+                                                       const Part2<R>* __restrict__ part_in,
+                                                       Part2<R>* __restrict__ part_out) {
+    extern __shared__ unsigned char lds_raw[];
+    R* ringb = reinterpret_cast<R*>(lds_raw);
+    const size_t off = (phi_ring_bytes<R, kTX, H>(TY) + 15) & ~size_t(15);
+    R* xch = reinterpret_cast<R*>(lds_raw + off);
+    Part2<R>* vs = reinterpret_cast<Part2<R>*>(lds_raw + off + lean_xch_bytes<R, TY>());
+    int x0, y0, za, zb;
+    tile_of_block(fs, kTX, g.nz, x0, y0, za, zb);
+    lean_tile<R, T, TY, H, W>(g, fin, fout, c, ringb, xch, vs, x0, y0, za, zb,
+                               phi_of<kTX>(const_cast<Part2<R>*>(part_in), g), part_out, phi_of<kTX>(part_out, g));
+}
+
+}  // namespace lbm

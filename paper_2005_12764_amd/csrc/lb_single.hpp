@@ -423,8 +423,6 @@ __device__ __forceinline__ void single_tile(const Geom& g, const Src& src, const
     const int x_ = x0 + tx_, y_ = y0 + ty_;
     const bool active = x_ < g.nx && y_ < g.ny;
     const int x1 = min(x0 + TX, g.nx), y1 = min(y0 + TY, g.ny);
-    Src srcr = src;
-    if constexpr (Src::ring) srcr.ring_plane_floats = rr.LY * RecRing<TX>::LX * 8;
     // edge lanes and the columns their x-face sums go to
     Part2<R>* const xf = part_out + g.N;
     int bd_lo = 0, bd_hi = 0;
@@ -469,7 +467,7 @@ __device__ __forceinline__ void single_tile(const Geom& g, const Src& src, const
                 if constexpr (Src::ring) {
                     const f4* const planes[3] = {rr.plane((cz - za) % 3), rr.plane((cz - za + 1) % 3),
                                                  rr.plane((cz - za + 2) % 3)};
-                    srcr.pull_ring(g, s, x, y, cz, t, d, planes, ty + 1, tx + 1, RecRing<TX>::LX);
+                    src.pull_ring(g, s, x, y, cz, t, d, planes, ty + 1, tx + 1, RecRing<TX>::LX);
                 } else {
                     src.pull(g, s, x, y, cz, t, d);
                 }

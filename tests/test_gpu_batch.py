@@ -126,3 +126,35 @@ def test_serving_loop_short_stream():
             B.step(r.steps)
             alone = B.totals(sl)
         assert np.array_equal(np.asarray(o.totals), alone)
+
+
+def test_f16_job_with_its_own_scale_matches_single_lattice():
+    # a batched fp16 job steps with its own deviation scale 2^scale_log2, as a
+    # single lattice with the same parameters does (bitwise: same tile code)
+    _, b, _ = _jobs(W.F16)
+    for s2 in (12, 20):
+        p = dict(b.params, storage=W.F16, scale_log2=s2)
+        with lb.Batch(2, 1 << 28, W.F16, graph_steps=10) as B:
+            sl = B.add(p, b.rho_r, b.rho_b, steps=30)
+            B.step(30)
+            batched = B.state(sl)
+        with lb.Lattice(dict(p, kernel=lb.KERNEL_TWOPASS)) as L:
+            L.init(b.rho_r, b.rho_b).step(30)
+            single = L.state()
+        assert np.array_equal(batched, single), s2
+
+
+def test_zero_step_16bit_job_is_rejected():
+    _, b, _ = _jobs(W.F16)
+    with lb.Batch(2, 1 << 28, W.F16, graph_steps=10) as B:
+        with pytest.raises(lb.LbError) as e:
+            B.add(b.params, b.rho_r, b.rho_b, steps=0)
+        assert e.value.code == lb.LB_EINVAL
+        assert B.free_bytes() == 1 << 28
+    with lb.Batch(2, 1 << 28, W.F32, graph_steps=10) as B:
+        p = dict(b.params, storage=W.F32)
+        sl = B.add(p, b.rho_r, b.rho_b, steps=0)     # raw storage keeps its initial state
+        f = B.state(sl)
+        with lb.Lattice(p) as L:
+            L.init(b.rho_r, b.rho_b)
+            assert np.array_equal(f, L.state())
