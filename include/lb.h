@@ -80,6 +80,11 @@ extern "C" {
 #define LB_TILES_ONE_READ 2 /* one-read step (rows 4, 8 or 16) */
 #define LB_TILES_BATCH 3    /* both passes of the batched step (rows 1, 2, 4 or 8) */
 
+/* Interface model (lb_params.model). */
+#define LB_MODEL_COLOUR_GRADIENT 0 /* colour gradient: perturbation, recolouring, near contact */
+#define LB_MODEL_SHAN_CHEN 1       /* Shan-Chen inter-component force with exact-difference
+                                      sources (Sec. 2.1, eq. shanchen_force with eq:edm) */
+
 /* Element type of caller fields. */
 #define LB_DTYPE_F64 0
 #define LB_DTYPE_F32 1
@@ -114,6 +119,14 @@ typedef struct {
                                between the components by the reflecting site's
                                rho_k/rho; edges get the sum of both faces' terms.
                                The sheared channel of Sec. 5 slides two walls at +-U. */
+    int32_t model;          /* LB_MODEL_*.  LB_MODEL_SHAN_CHEN replaces the perturbation,
+                               recolouring and near-contact force (A, beta, nc_* unused) by
+                               the force F^k(x) = -g_sc rho_k(x) sum_i w_i rho_k'(x + c_i) c_i
+                               on each component k (k' the other one; a neighbour beyond a
+                               wall is its mirror image), entering each component's
+                               exact-difference source with its share (rho_k/rho) of the
+                               body force.  Raw storage (F64, F32) and two-pass steps only. */
+    double g_sc;            /* Shan-Chen coupling G_C (> 0 repels the components) */
 } lb_params;
 
 /* Create a lattice on the current HIP device.  Allocates the two population

@@ -57,6 +57,8 @@ struct Coeffs {
     R fx, fy, fz;          // body force density
     int nc_range;          // 0 = near-contact off
     int same_tau;          // tau_r == tau_b: omega above holds everywhere
+    int model;             // 0 colour gradient, 1 Shan-Chen
+    R g_sc;                // Shan-Chen coupling G_C
 };
 
 // Reciprocal and reciprocal square root.  FP32: the hardware estimates
@@ -170,6 +172,69 @@ __device__ __forceinline__ void collide(R (&t)[Q], R (&d)[Q], R gx, R gy, R gz, 
         tot->vx = seg * nx;
         tot->vy = seg * ny;
         tot->vz = seg * nz;
+    }
+}
+
+// Local collision of one site in the Shan-Chen model (Sec. 2.1: the
+// inter-component force of eq. shanchen_force entering each component's
+// exact-difference source, eq:edm), in the shifted variables of collide().
+// (bx,by,bz) = sum_i w_i rho_b(x + c_i) c_i and (rx,ry,rz) the same of rho_r.
+// Component k gets the velocity shift du_k = F^k/rho_k with
+// F^k = -G_C rho_k sum_i w_i rho_k'(x + c_i) c_i + (rho_k/rho) F_body, i.e.
+// du_k = -G_C (that sum) + F_body/rho, with no division by rho_k; both relax
+// with the mixture rate toward f^eq(rho_k, u), u = j/rho.  No perturbation
+// and no recolouring: the force alone keeps the components apart.
+template <typename R>
+__device__ __forceinline__ void collide_sc(R (&t)[Q], R (&d)[Q], R bx, R by, R bz, R rx, R ry, R rz,
+                                           const Coeffs<R>& c) {
+    using L = Lattice;
+    R drho = R(0), dif = R(0), rc = R(0), jx = R(0), jy = R(0), jz = R(0);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        drho += t[i];
+        dif += d[i];
+        rc += weight<R>(i) + t[i];
+        if (L::cx[i]) jx += L::cx[i] > 0 ? t[i] : -t[i];
+        if (L::cy[i]) jy += L::cy[i] > 0 ? t[i] : -t[i];
+        if (L::cz[i]) jz += L::cz[i] > 0 ? t[i] : -t[i];
+    }
+    const R rho = R(1) + drho;
+    const R rr = R(0.5) * (rc + dif), rb = R(0.5) * (rc - dif);
+    const R inv_rho = R(1) / rho;
+    const R ux = jx * inv_rho, uy = jy * inv_rho, uz = jz * inv_rho;
+    const R fx = c.fx * inv_rho, fy = c.fy * inv_rho, fz = c.fz * inv_rho;
+    // velocity shifts of the red (R) and blue (B) components
+    const R Rx = fx - c.g_sc * bx, Ry = fy - c.g_sc * by, Rz = fz - c.g_sc * bz;
+    const R Bx = fx - c.g_sc * rx, By = fy - c.g_sc * ry, Bz = fz - c.g_sc * rz;
+    // s_k = u + (u + du_k): f^eq(rho_k, u + du_k) - f^eq(rho_k, u)
+    //   = rho_k w_i [3 c.du_k + 4.5 (c.du_k)(c.s_k) - 1.5 du_k.s_k]
+    const R sRx = R(2) * ux + Rx, sRy = R(2) * uy + Ry, sRz = R(2) * uz + Rz;
+    const R sBx = R(2) * ux + Bx, sBy = R(2) * uy + By, sBz = R(2) * uz + Bz;
+    const R dsR = Rx * sRx + Ry * sRy + Rz * sRz;
+    const R dsB = Bx * sBx + By * sBy + Bz * sBz;
+    R omega = c.omega;
+    if (!c.same_tau) {
+        const R phi = dif / rc;
+        const R xr = R(0.5) + R(0.5) * phi, xb = R(0.5) - R(0.5) * phi;
+        const R nubar = R(1) / (xr * c.inv_nu_r + xb * c.inv_nu_b);
+        omega = R(2) / (R(6) * nubar + R(1));
+    }
+    const R uu = ux * ux + uy * uy + uz * uz;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const R w = weight<R>(i);
+        const R cu = R(L::cx[i]) * ux + R(L::cy[i]) * uy + R(L::cz[i]) * uz;
+        const R q = R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu;
+        const R teq = w * (drho + rho * q);          // f^eq(rho_r) + f^eq(rho_b) - w
+        const R deq = w * dif * (R(1) + q);          // f^eq(rho_r) - f^eq(rho_b)
+        const R cdR = R(L::cx[i]) * Rx + R(L::cy[i]) * Ry + R(L::cz[i]) * Rz;
+        const R csR = R(L::cx[i]) * sRx + R(L::cy[i]) * sRy + R(L::cz[i]) * sRz;
+        const R cdB = R(L::cx[i]) * Bx + R(L::cy[i]) * By + R(L::cz[i]) * Bz;
+        const R csB = R(L::cx[i]) * sBx + R(L::cy[i]) * sBy + R(L::cz[i]) * sBz;
+        const R SR = rr * w * (R(3) * cdR + R(4.5) * cdR * csR - R(1.5) * dsR);
+        const R SB = rb * w * (R(3) * cdB + R(4.5) * cdB * csB - R(1.5) * dsB);
+        t[i] = t[i] - omega * (t[i] - teq) + (SR + SB);
+        d[i] = d[i] - omega * (d[i] - deq) + (SR - SB);
     }
 }
 

@@ -57,6 +57,16 @@ int validate_params(const lb_params* p, std::string& why) {
             if (!std::isfinite(p->wall_velocity[f][a])) return why = "wall_velocity must be finite", LB_EINVAL;
     if (p->scale_log2 < 0 || p->scale_log2 > 24) return why = "scale_log2 outside 0..24", LB_EINVAL;
     if (!std::isfinite(p->eps_g) || !std::isfinite(p->g_iface)) return why = "eps_g, g_iface must be finite", LB_EINVAL;
+    if (p->model != LB_MODEL_COLOUR_GRADIENT && p->model != LB_MODEL_SHAN_CHEN)
+        return why = "unknown interface model", LB_EINVAL;
+    if (p->model == LB_MODEL_SHAN_CHEN) {
+        if (!std::isfinite(p->g_sc)) return why = "g_sc must be finite", LB_EINVAL;
+        // the 16-bit codec stores the colour part in the form recolouring gives
+        if (p->storage != LB_STORE_F64 && p->storage != LB_STORE_F32)
+            return why = "the Shan-Chen model needs raw storage (LB_STORE_F64 or LB_STORE_F32)", LB_EINVAL;
+        if (p->kernel == LB_KERNEL_FUSED)
+            return why = "the Shan-Chen model steps with two passes (LB_KERNEL_AUTO or LB_KERNEL_TWOPASS)", LB_EINVAL;
+    }
     return LB_OK;
 }
 
@@ -81,7 +91,9 @@ Coeffs<R> make_coeffs(const lb_params& p) {
     c.fx = R(p.body_force[0]);
     c.fy = R(p.body_force[1]);
     c.fz = R(p.body_force[2]);
-    c.nc_range = (p.nc_strength > 0.0) ? p.nc_range : 0;
+    c.nc_range = (p.nc_strength > 0.0 && p.model == LB_MODEL_COLOUR_GRADIENT) ? p.nc_range : 0;
+    c.model = p.model;
+    c.g_sc = R(p.g_sc);
     return c;
 }
 template Coeffs<double> make_coeffs<double>(const lb_params&);
@@ -214,10 +226,10 @@ int64_t lb_footprint_bytes(const lb_params* p) {
     if (validate_params(p, why) != LB_OK) return -1;
     const size_t N = size_t(p->nx) * p->ny * p->nz;
     const size_t real = p->storage == LB_STORE_F64 ? 8 : 4;
-    size_t b = 2 * pop_bytes(p->storage, N) + N * real;
+    size_t b = 2 * pop_bytes(p->storage, N) + N * real * (p->model == LB_MODEL_SHAN_CHEN ? 2 : 1);
     // phase sums of the one-read step (raw storage unless two passes are asked
     // for; an upper bound for lattices the automatic choice steps otherwise)
-    if (p->storage <= LB_STORE_F32 && p->kernel != LB_KERNEL_TWOPASS)
+    if (p->storage <= LB_STORE_F32 && p->kernel != LB_KERNEL_TWOPASS && p->model == LB_MODEL_COLOUR_GRADIENT)
         b += 2 * part_reals<kTX>(p->nx, p->ny, p->nz) * real;
     return (int64_t)b;
 }
@@ -248,7 +260,9 @@ int lb_create(const lb_params* params, void* hip_stream, lb_t** out) {
     int rc = LB_OK;
     if ((rc = check_hip(hipMalloc(&h->buf[0], pb), "hipMalloc populations")) ||
         (rc = check_hip(hipMalloc(&h->buf[1], pb), "hipMalloc populations")) ||
-        (rc = check_hip(hipMalloc(&h->phi, N * (h->p.storage == LB_STORE_F64 ? 8 : 4)), "hipMalloc phase field")) ||
+        (rc = check_hip(hipMalloc(&h->phi, N * (h->p.storage == LB_STORE_F64 ? 8 : 4) *
+                                               (h->p.model == LB_MODEL_SHAN_CHEN ? 2 : 1)),
+                        "hipMalloc phase field")) ||
         (rc = check_hip(hipMalloc((void**)&h->partial, sizeof(Neu) * NTOT * kTotalsBlocks), "hipMalloc partials")) ||
         (rc = check_hip(hipMalloc((void**)&h->dtot, sizeof(double) * 2 * NTOT), "hipMalloc totals"))) {
         release(h);

@@ -538,6 +538,8 @@ static int batch_admit(lb_batch_t* b, const lb_params* params, int64_t steps, in
     const int K = params->nc_strength > 0.0 ? params->nc_range : 0;
     if (K + 1 > kBatchH) return bfail(LB_EINVAL, "batched jobs support near-contact ranges up to 2");
     if (make_geom(*params).moving) return bfail(LB_EINVAL, "batched jobs do not support moving walls");
+    if (params->model != LB_MODEL_COLOUR_GRADIENT)
+        return bfail(LB_EINVAL, "batched jobs use the colour-gradient model");
     if (steps < 0) return bfail(LB_EINVAL, "steps must be >= 0");
     // a 16-bit job's raw FP32 initial state lives in the shared staging area
     // only until its first step (taken here) encodes it into its own buffers

@@ -10,6 +10,7 @@
 #include "lb_internal.hpp"
 #include "lb_korteweg.hpp"
 #include "lb_lean.hpp"
+#include "lb_shanchen.hpp"
 #include "lb_single.hpp"
 
 namespace lbm {
@@ -203,9 +204,34 @@ int phase_pass(const LatticeView& v, const Src& src) {
 // Two passes: the phase pass writes phi; the collide pass z-marches tiles
 // with phi in an LDS ring (or, when the ring does not fit, reads phi from
 // global memory site by site).
+// Shan-Chen step (raw storage): density pass, then the collide tiles with the
+// density pairs in an LDS ring.
+template <typename R, typename Src, typename Dst>
+int sc_two_pass(const LatticeView& v, const Src& src, const Dst& dst, const Coeffs<R>& c, const StepEvents* t) {
+    if constexpr (Src::ring || Dst::ring) {
+        return set_error(LB_EINVAL, "the Shan-Chen model needs raw storage");
+    } else {
+        if (t) (void)hipEventRecord(t->ev[0], v.stream);
+        RhoPair<R>* rho2 = (RhoPair<R>*)v.phi;
+        hipLaunchKernelGGL((sc_density_kernel<R, Src>), dim3(grid_for(v.g.N)), dim3(kBlock), 0, v.stream, v.g, src,
+                           rho2);
+        int rc = launch_status("sc_density_kernel");
+        if (rc) return rc;
+        if (t) (void)hipEventRecord(t->ev[1], v.stream);
+        const FusedShape fs = tile_shape(*v.p, TILE_COLLIDE);
+        const size_t lds = sc_ring_bytes<R>(fs.TY, kTX);
+        hipLaunchKernelGGL((sc_collide_kernel<R, Src, Dst, kTX>), dim3(fs.nblocks), dim3(kBlock), lds, v.stream, v.g,
+                           src, dst, c, fs, (const RhoPair<R>*)rho2);
+        rc = launch_status("sc_collide_kernel");
+        if (t) (void)hipEventRecord(t->ev[2], v.stream);
+        return rc;
+    }
+}
+
 template <typename R, typename Src, typename Dst>
 int two_pass(const LatticeView& v, const Src& src, const Dst& dst, const Coeffs<R>& c, const StepEvents* t) {
     if (!v.phi) return set_error(LB_EINVAL, "two-pass step without a phase-field buffer");
+    if (v.p->model == LB_MODEL_SHAN_CHEN) return sc_two_pass<R>(v, src, dst, c, t);
     if (t) (void)hipEventRecord(t->ev[0], v.stream);
     int rc = phase_pass<R>(v, src);
     if (rc) return rc;
@@ -247,7 +273,9 @@ TileSetting tile_setting(int kind, int storage) {
 }
 void set_tile_setting(int kind, int storage, int ty, int tz) { g_tiles[kind][storage] = TileSetting{ty, tz}; }
 
-int tile_halo(const lb_params& p) { return 1 + ((p.nc_strength > 0.0) ? p.nc_range : 0); }
+int tile_halo(const lb_params& p) {
+    return 1 + ((p.nc_strength > 0.0 && p.model == LB_MODEL_COLOUR_GRADIENT) ? p.nc_range : 0);
+}
 
 size_t tile_lds(const lb_params& p, int kind, int TY) {
     const int H = tile_halo(p);
@@ -345,7 +373,8 @@ int choose_kernel(const lb_params& p) {
         for (int k = 0; k < 3; ++k) moving |= p.bc[f / 2] != 0 && p.wall_velocity[f][k] != 0.0;
     // (the one-read step's 32-bit byte offsets need 10 x sites x value size < 2^32)
     const bool small = (uint64_t)kResArrays * real_size(p) * (uint64_t)p.nx * p.ny * p.nz < ((uint64_t)1 << 32);
-    if (split_storage(p) || moving || !fits || !small) return LB_KERNEL_TWOPASS;
+    if (split_storage(p) || moving || !fits || !small || p.model != LB_MODEL_COLOUR_GRADIENT)
+        return LB_KERNEL_TWOPASS;
     return LB_KERNEL_FUSED;
 }
 

@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "liblb.so")
 
 LB_OK, LB_EINVAL, LB_ENOMEM, LB_EDEVICE, LB_ESTATE = 0, -1, -2, -3, -4
 KERNEL_AUTO, KERNEL_TWOPASS, KERNEL_FUSED = 0, 1, 2
+MODEL_COLOUR_GRADIENT, MODEL_SHAN_CHEN = 0, 1
 DTYPE_F64, DTYPE_F32 = 0, 1
 MAX_NC_RANGE = 4
 Q = 19
@@ -45,6 +46,7 @@ class lb_params(ctypes.Structure):
         ("body_force", ctypes.c_double * 3),
         ("eps_g", ctypes.c_double), ("g_iface", ctypes.c_double),
         ("wall_velocity", (ctypes.c_double * 3) * 6),
+        ("model", ctypes.c_int32), ("g_sc", ctypes.c_double),
     ]
 
 
@@ -65,6 +67,8 @@ def make_params(p: dict) -> lb_params:
     s.nc_hmin = float(p.get("nc_hmin", 2.0))
     s.eps_g = float(p.get("eps_g", 0.0))
     s.g_iface = float(p.get("g_iface", 0.0))
+    s.model = int(p.get("model", MODEL_COLOUR_GRADIENT))
+    s.g_sc = float(p.get("g_sc", 0.0))
     uw = p.get("wall_velocity")
     if uw is not None:
         uw = np.asarray(uw, dtype=np.float64).reshape(6, 3)

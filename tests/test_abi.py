@@ -26,13 +26,26 @@ def test_library_exports_every_declared_function():
     assert not missing, missing
 
 
-def test_params_struct_matches_header_size():
-    assert ctypes.sizeof(lb.lb_params) == 128 + 6 * 3 * 8
+def test_params_struct_matches_header_size(tmp_path):
+    # the ctypes mirror against the C compiler's layout of include/lb.h
+    import subprocess
+    src = tmp_path / "size.c"
+    src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "lb.h"\n'
+                   'int main(void){printf("%zu %zu %zu\\n", sizeof(lb_params),'
+                   ' offsetof(lb_params, model), offsetof(lb_params, g_sc)); return 0;}\n')
+    exe = tmp_path / "size"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run(["gcc", "-I", inc, "-o", str(exe), str(src)], check=True)
+    size, off_model, off_gsc = (int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                                 check=True).stdout.split())
+    assert ctypes.sizeof(lb.lb_params) == size == 128 + 6 * 3 * 8 + 16
+    assert lb.lb_params.model.offset == off_model and lb.lb_params.g_sc.offset == off_gsc
 
 
 @pytest.mark.parametrize("bad", [
     dict(nx=0), dict(tau_r=0.5), dict(tau_b=0.2), dict(nc_range=5), dict(storage=7),
     dict(kernel=9), dict(beta=1.5), dict(A=-1.0), dict(bc=(0, 2, 0)), dict(nc_strength=-0.1),
+    dict(model=2), dict(model=1, storage=2), dict(model=1, kernel=2), dict(model=1, g_sc=float("nan")),
 ])
 def test_create_rejects_invalid_parameters(bad):
     p = W.base_params(8, 8, 8, storage=W.F32)
