@@ -293,6 +293,26 @@ int64_t lb_batch_free_bytes(const lb_batch_t* b);
 
 int lb_batch_destroy(lb_batch_t* b);
 
+/* ------------------------------------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the seven
+ * compensated totals of lb_moments (same order and meaning: red mass, blue
+ * mass, momentum x, y, z, kinetic energy, non-finite or non-positive sites;
+ * (sum, correction) pairs) of a population state the caller holds in device
+ * memory, in the layout of lb_get_state ([2][19][N], f^r then f^b; dtype
+ * LB_DTYPE_F64 or LB_DTYPE_F32).  params: only nx, ny, nz are read.
+ * totals: device memory, 14 doubles.  Enqueued on hip_stream (NULL = the
+ * default stream); does not synchronise.  Allocates nothing: the per-block
+ * partial sums live in a static array of the library (512 x 7 (sum,
+ * correction) pairs = 57,344 bytes on each device it runs on, held until the
+ * process ends), shared by every call on that device, so calls that overlap
+ * on one device race; every call rewrites all of it before reading it.
+ * Errors: LB_EINVAL (NULL pointer, bad dtype, size < 1 or >= 2^31 sites),
+ * LB_EDEVICE (no device, launch failure).
+ * ------------------------------------------------------------------------ */
+int lb_state_totals_noalloc(const lb_params* params, const void* f, int32_t dtype, double* totals,
+                            void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

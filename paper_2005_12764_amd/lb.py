@@ -129,6 +129,7 @@ def lib():
         "lb_batch_job_steps": ([vp, i32], i64),
         "lb_batch_free_bytes": ([vp], i64),
         "lb_batch_destroy": ([vp], i32),
+        "lb_state_totals_noalloc": ([pp, vp, i32, vp, vp], i32),
     }
     for name, (args, res) in sig.items():
         if hasattr(L, name):
@@ -245,6 +246,26 @@ def lb_moments(h, rho_r=None, rho_b=None, mom=None, want_totals: bool = False):
         t = np.array(tot[:], dtype=np.float64).reshape(7, 2)
         return t
     return None
+
+
+def lb_state_totals_noalloc(params: dict, f, totals, stream=None) -> None:
+    """The 7 compensated totals (sum, correction pairs) of a population
+    state f ([2][19][nz][ny][nx] torch device tensor, float64 or float32, the
+    layout of lb_get_state) into `totals` (torch float64 device tensor of 14),
+    ordered on `stream`; the library allocates nothing for it."""
+    if not (_is_torch(f) and f.is_cuda and _is_torch(totals) and totals.is_cuda):
+        raise ValueError("f and totals must be device tensors")
+    if totals.dtype != torch_float64() or totals.numel() != 14 or not totals.is_contiguous():
+        raise ValueError("totals must be a contiguous float64 tensor of 14 values")
+    pf, _, code, _ = _arg(f)
+    prm = make_params(params)
+    _check(lib().lb_state_totals_noalloc(ctypes.byref(prm), pf, code, ctypes.c_void_p(totals.data_ptr()),
+                                         _stream_ptr(stream)))
+
+
+def torch_float64():
+    import torch
+    return torch.float64
 
 
 TILES_PHASE, TILES_COLLIDE, TILES_ONE_READ, TILES_BATCH = 0, 1, 2, 3
