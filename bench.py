@@ -23,8 +23,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes per site update: 2 components x 19 populations x (read + write)
-ALGO_BYTES = {0: 2 * 19 * 2 * 8, 1: 2 * 19 * 2 * 4, 2: 2 * 19 * 2 * 2, 3: 2 * 19 * 2 * 2}
+# algorithmic bytes per site update, read + write: raw storage 2 components x
+# 19 populations; 16-bit moment-split storage a 32-byte FP32 record plus 19
+# 16-bit deviations per site (the plain 16-bit form of the same state would
+# be 2 x 19 x 2 x 2 = 152 B)
+ALGO_BYTES = {0: 2 * 19 * 2 * 8, 1: 2 * 19 * 2 * 4, 2: 2 * (32 + 19 * 2), 3: 2 * (32 + 19 * 2)}
 STORE_NAME = {0: "f64", 1: "f32", 2: "f16", 3: "bf16"}
 
 
@@ -255,9 +258,8 @@ def korteweg_leg(w, stream, b=4, reps=20):
 
 def cpu_baseline(w, steps, steps_1t):
     from oracle import oracle as O
-    from tests.helpers import oracle_params
 
-    prm = oracle_params(dict(w.params, storage=0))
+    prm = O.params_from_dict(dict(w.params, storage=0))
     f = O.init(prm, w.rho_r, w.rho_b)
     t0 = time.perf_counter()
     O.step(prm, f, steps)
@@ -288,7 +290,8 @@ def main():
     ap.add_argument("--n", type=int, default=256, help="lattice side of the emulsion")
     ap.add_argument("--variants", default="f32,f16,bf16")
     ap.add_argument("--kernel", type=int, default=0, help="0 auto, 1 two-pass, 2 fused")
-    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=16,
+                    help="oracle steps of the full lattice on all host threads (about 30 s on 16)")
     ap.add_argument("--cpu-steps-1t", type=int, default=1, help="oracle steps on one thread (0 = skip)")
     ap.add_argument("--serve-jobs", type=int, default=200, help="jobs of the serving leg (0 = skip)")
     ap.add_argument("--serve-rate", type=float, default=40.0)

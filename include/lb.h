@@ -129,8 +129,11 @@ typedef struct {
     double g_sc;            /* Shan-Chen coupling G_C (> 0 repels the components) */
 } lb_params;
 
-/* Create a lattice on the current HIP device.  Allocates the two population
- * buffers (ping-pong) and the phase-field scratch; the library owns them.
+/* Create a lattice on the current HIP device: the problem statement of
+ * Sec. 2 (D3Q19 populations on a cubic lattice, eq:eq1 to eq:equil) for the
+ * two components of Sec. 2.1 (eq:twobgk), with the relaxation times, forces
+ * and boundaries of lb_params.  Allocates the two population buffers
+ * (ping-pong) and the phase-field scratch; the library owns them.
  * hip_stream: a hipStream_t to order all work on, or NULL for the default
  * stream.  On success *out is a new handle; nothing is allocated on failure.
  * LB_EINVAL: size < 1, tau <= 1/2, nc_range outside 0..LB_MAX_NC_RANGE,
@@ -152,7 +155,13 @@ int lb_init_fields(lb_t* h, const void* rho_r, const void* rho_b, const void* u,
 int lb_init_droplets(lb_t* h, const double* centres, const double* radii, int32_t n, double width,
                      double background, double rho0);
 
-/* Enqueue n >= 0 full steps (collide, then stream). */
+/* Enqueue n >= 0 full steps of the update: collision with the mixture BGK
+ * rate (Sec. 2.1, eq:twobgk; Sec. 2, eq:eq3), the exact-difference force
+ * source (Sec. 2.1, eq:edm) of the body force plus the near-contact force
+ * (Sec. 4, F_rep equation), the colour-gradient perturbation and recolouring
+ * (or the Shan-Chen force of Sec. 2.1, eq. shanchen_force, per lb_params.model),
+ * then streaming (Sec. 2, after eq:eq3) with periodic or bounce-back axes.
+ * LB_ESTATE before lb_init_fields; LB_EDEVICE when a launch fails. */
 int lb_step(lb_t* h, int32_t n);
 
 /* As lb_step, timing every pass with HIP events on the handle's stream;
@@ -213,7 +222,8 @@ int64_t lb_step_count(const lb_t* h);
 /* Kernel lb_step actually uses (LB_KERNEL_TWOPASS or LB_KERNEL_FUSED). */
 int lb_kernel_in_use(const lb_t* h);
 
-/* Release every buffer of the handle (after finishing its queued work). */
+/* Release every buffer of the handle (after finishing its queued work); the
+ * handle is invalid afterwards. */
 int lb_destroy(lb_t* h);
 
 /* Message of the calling thread's last failure ("" if none). */

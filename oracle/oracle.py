@@ -122,6 +122,21 @@ class Params:
                         dtype=np.float64)
 
 
+def params_from_dict(p: dict, eps_g=None, g_iface: float = 0.05) -> Params:
+    """Oracle parameters for a parameter dict with the library's keys (the
+    same physical quantities); eps_g defaults to 1e-12 for FP64 storage
+    (storage 0) and 1e-6 otherwise, the thresholds the GPU library uses."""
+    if eps_g is None:
+        eps_g = 1e-12 if int(p.get("storage", 0)) == 0 else 1e-6
+    return Params(nx=p["nx"], ny=p["ny"], nz=p["nz"], bc=tuple(p["bc"]),
+                  tau_r=p["tau_r"], tau_b=p["tau_b"], A=p["A"], beta=p["beta"],
+                  nc_strength=p["nc_strength"], nc_range=p["nc_range"],
+                  nc_hmin=p["nc_hmin"], body_force=tuple(p["body_force"]),
+                  eps_g=eps_g, g_iface=g_iface,
+                  wall_velocity=tuple(map(tuple, p.get("wall_velocity", ((0.0, 0.0, 0.0),) * 6))),
+                  model=int(p.get("model", 0)), g_sc=float(p.get("g_sc", 0.0)))
+
+
 def tables():
     c = np.zeros((Q, 3), dtype=np.int32)
     w = np.zeros(Q)

@@ -1,24 +1,15 @@
 """Shared test helpers: parameter conversion and the parity metrics."""
 from __future__ import annotations
 
+import math
+
 import numpy as np
 
 from oracle import oracle as O
 
-EPS_G = {0: 1e-12, 1: 1e-6, 2: 1e-6, 3: 1e-6}
-
-
 def oracle_params(p: dict, eps_g=None, g_iface=0.05) -> O.Params:
     """Oracle parameters for a library parameter dict (same quantities)."""
-    if eps_g is None:
-        eps_g = EPS_G[int(p.get("storage", 0))]
-    return O.Params(nx=p["nx"], ny=p["ny"], nz=p["nz"], bc=tuple(p["bc"]),
-                    tau_r=p["tau_r"], tau_b=p["tau_b"], A=p["A"], beta=p["beta"],
-                    nc_strength=p["nc_strength"], nc_range=p["nc_range"],
-                    nc_hmin=p["nc_hmin"], body_force=tuple(p["body_force"]),
-                    eps_g=eps_g, g_iface=g_iface,
-                    wall_velocity=tuple(map(tuple, p.get("wall_velocity", ((0.0, 0.0, 0.0),) * 6))),
-                    model=int(p.get("model", 0)), g_sc=float(p.get("g_sc", 0.0)))
+    return O.params_from_dict(p, eps_g=eps_g, g_iface=g_iface)
 
 
 def rel_l2(a, b):
@@ -52,3 +43,33 @@ def state_errors(f, f_ref):
     errs["max_abs"] = float(np.abs(f - f_ref).max())
     errs["worst"] = max(errs["populations"], errs["rho_r"], errs["rho_b"], errs["momentum"])
     return errs
+
+
+def duct_series(a, b, y, z, g, nu, nmax=199):
+    """Steady duct flow u(y, z) for a width a (y in [-a/2, a/2]) by height b
+    (z in [-b/2, b/2]) cross-section under force density g: the plane profile
+    (g / 2 nu)(a^2/4 - y^2), expanded in cos(n pi y / a) over odd n, corrected
+    by the cosh(n pi z / a) terms that vanish at z = +-b/2."""
+    u = np.zeros(np.broadcast(y, z).shape)
+    for n in range(1, nmax + 1, 2):
+        u += ((-1) ** ((n - 1) // 2) / n ** 3
+              * (1 - np.cosh(n * math.pi * z / a) / np.cosh(n * math.pi * b / (2 * a)))
+              * np.cos(n * math.pi * y / a))
+    return 4 * g * a * a / (nu * math.pi ** 3) * u
+
+
+def structure_factor(phi):
+    """Shell-averaged |FFT(phi - <phi>)|^2 of a cubic field: the first
+    moment k1 = sum k S / sum S and the peak height (k in units of 2 pi / n)."""
+    n = phi.shape[0]
+    f = np.fft.fftn(phi - phi.mean())
+    p = (f.real ** 2 + f.imag ** 2).ravel()
+    k1d = np.fft.fftfreq(n, d=1.0 / n)
+    kz, ky, kx = np.meshgrid(k1d, k1d, k1d, indexing="ij")
+    kk = np.rint(np.sqrt(kx ** 2 + ky ** 2 + kz ** 2)).astype(int).ravel()
+    m = kk <= n // 2
+    S = np.bincount(kk[m], weights=p[m], minlength=n // 2 + 1)
+    cnt = np.bincount(kk[m], minlength=n // 2 + 1)
+    S = S / np.maximum(cnt, 1)
+    k = np.arange(n // 2 + 1)
+    return float((k[1:] * S[1:]).sum() / S[1:].sum()), float(S[1:].max())

@@ -83,11 +83,18 @@ def threshold_sites(prm, G, K, g_i, eps_g):
     return near
 
 
-@pytest.mark.parametrize("shape", [(64, 64, 64), (64, 64, 128)], ids=["64^3", "128x64x64"])
-def test_one_step_differs_from_the_oracle_only_at_threshold_sites(shape):
-    p, rr, rb = emulsion(shape)
+@pytest.mark.parametrize("case", ["emulsion 64^3", "emulsion 128x64x64", "spinodal 64^3"])
+def test_one_step_differs_from_the_oracle_only_at_threshold_sites(case):
+    if case.startswith("spinodal"):
+        # the spinodal set-up once domains have formed (near contact 0.03)
+        w = W.spinodal(seed=0, n=64, storage=W.F32)
+        p, rr, rb, before = w.params, w.rho_r, w.rho_b, 100
+    else:
+        shape = (64, 64, 64) if case.endswith("64^3") else (64, 64, 128)
+        (p, rr, rb), before = emulsion(shape), 199
+    shape = rr.shape
     with lb.Lattice(p) as L:
-        L.init(rr, rb).step(199)
+        L.init(rr, rb).step(before)
         f0 = L.state()
     lb.lb_set_tiles(lb.TILES_ONE_READ, W.F32, 16, 0)
     try:
@@ -106,8 +113,8 @@ def test_one_step_differs_from_the_oracle_only_at_threshold_sites(shape):
     bad = err > 1e-6 * scale                               # beyond FP32 rounding
     near = threshold_sites(prm, G, p["nc_range"], 0.05, 1e-6)
     n = bad.size
-    print("shape %s: %d sites differ, %d near a threshold (of %d); differing not near: %d"
-          % (shape, bad.sum(), near.sum(), n, (bad & ~near).sum()), flush=True)
+    print("%s: %d sites differ, %d near a threshold (of %d); differing not near: %d"
+          % (case, bad.sum(), near.sum(), n, (bad & ~near).sum()), flush=True)
     assert not (bad & ~near).any()
     assert near.sum() < 0.01 * n
     # the remaining sites: the FP32 bound

@@ -5,6 +5,9 @@
   u(y) = g/(2 nu) (y + 1/2)(H - 1/2 - y) to round-off at tau = 1/2 + sqrt(3)/4,
   and second-order accurate at other tau (Sec. 2 eq:eq1 to eq:eq3, Sec. 2.1
   eq:edm);
+- rectangular-duct flow (walls in y and z, force along x): the discrete
+  steady state converges at second order to the Fourier-series solution of
+  the duct (the corners keep it from being exact at the magic tau);
 - a shear wave decays at nu k^2 with the mixture viscosity of Sec. 2.1
   eq:twobgk (harmonic mean weighted by the component densities);
 - Laplace's law for a static disc: the pressure jump times the radius is
@@ -19,7 +22,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_2005_12764_amd import workloads as W
-from tests.helpers import oracle_params
+from tests.helpers import duct_series, oracle_params
 
 
 def _poiseuille(H, tau, g, steps):
@@ -42,6 +45,28 @@ def test_poiseuille_exact_at_magic_tau():
     err, ux, ua = _poiseuille(H, tau, 1e-6, int(20 * H * H / nu))
     assert err < 1e-10
     assert np.allclose(ux, ux[::-1], rtol=1e-12)        # symmetric about the mid-plane
+
+
+def _duct(a, b, tau, g=1e-6):
+    nu = (tau - 0.5) / 3
+    p = W.base_params(2, a, b, bc=(0, 1, 1), storage=W.F64, tau_r=tau, tau_b=tau, body_force=(g, 0.0, 0.0))
+    rr = np.ones((b, a, 2))
+    prm = oracle_params(p)
+    steps = int(36 * b * b / (nu * math.pi ** 2))       # the slowest mode decays by e^-36
+    f = O.step(prm, O.init(prm, rr, np.zeros_like(rr)), steps)
+    r1, r2, j = O.moments(prm, f)
+    ux = ((j[0] + g / 2) / (r1 + r2))[:, :, 0]
+    y = np.arange(a) - (a - 1) / 2
+    z = np.arange(b) - (b - 1) / 2
+    ua = duct_series(a, b, y[None, :], z[:, None], g, nu)
+    return float(np.linalg.norm(ux - ua) / np.linalg.norm(ua))
+
+
+def test_duct_flow_converges_to_the_fourier_series():
+    tau = 0.5 + math.sqrt(3) / 4
+    e1, e2 = _duct(16, 8, tau), _duct(32, 16, tau)
+    assert e1 < 3e-3 and e2 < 6e-4
+    assert 3.5 < e1 / e2 < 5.5                          # second order in the cross-section
 
 
 def test_poiseuille_second_order_at_unit_tau():
