@@ -59,10 +59,11 @@ extern "C" {
 /* Population storage. */
 #define LB_STORE_F64 0  /* raw FP64 populations, 2 x 19 x 8 B per site */
 #define LB_STORE_F32 1  /* raw FP32 populations, 2 x 19 x 4 B per site */
-#define LB_STORE_F16 2  /* 16-bit moment-split: per site FP32 rho, u, red fraction and
-                           recolouring vector (32 B) + per direction the deviation of
-                           the total population from its local equilibrium in fp16,
-                           scaled by 2^scale_log2 (38 B); computes in FP32 */
+#define LB_STORE_F16 2  /* 16-bit moment-split: per site FP32 density, momentum term of
+                           the equilibrium, phase and recolouring vector (32 B) + per
+                           direction the deviation of the total population from the
+                           equilibrium's first-order part in fp16, scaled by
+                           2^scale_log2 (38 B); computes in FP32 */
 #define LB_STORE_BF16 3 /* as LB_STORE_F16 with bf16 deviations (no scale) */
 
 /* Kernel selection for lb_step. */

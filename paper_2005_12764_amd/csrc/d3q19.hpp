@@ -82,8 +82,9 @@ __device__ __forceinline__ double inv_norm(double g2) { return 1.0 / sqrt(g2); }
 // Outputs of one site's collision that the 16-bit storage keeps per site.
 template <typename R>
 struct SiteTotals {
-    R drho, ux, uy, uz;    // post-collision density - 1 and velocity (j + F)/rho
-    R xr;                  // red fraction rho_r/rho
+    R drho;                // post-collision density - 1
+    R jx, jy, jz;          // 3 (j + F) = 3 rho v: the linear term of the equilibrium
+    R phi;                 // phase x_r - x_b
     R vx, vy, vz;          // recolouring vector beta (rho_r rho_b/rho) G/|G|
 };
 
@@ -165,10 +166,10 @@ __device__ __forceinline__ void collide(R (&t)[Q], R (&d)[Q], R gx, R gy, R gz, 
     }
     if (tot) {
         tot->drho = drho;
-        tot->ux = vx;  // (j + F)/rho
-        tot->uy = vy;
-        tot->uz = vz;
-        tot->xr = xr;
+        tot->jx = R(3) * rho * vx;  // v = (j + F)/rho
+        tot->jy = R(3) * rho * vy;
+        tot->jz = R(3) * rho * vz;
+        tot->phi = phi;
         tot->vx = seg * nx;
         tot->vy = seg * ny;
         tot->vz = seg * nz;

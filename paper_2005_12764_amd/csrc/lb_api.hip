@@ -227,10 +227,12 @@ int64_t lb_footprint_bytes(const lb_params* p) {
     const size_t N = size_t(p->nx) * p->ny * p->nz;
     const size_t real = p->storage == LB_STORE_F64 ? 8 : 4;
     size_t b = 2 * pop_bytes(p->storage, N) + N * real * (p->model == LB_MODEL_SHAN_CHEN ? 2 : 1);
-    // phase sums of the one-read step (raw storage unless two passes are asked
-    // for; an upper bound for lattices the automatic choice steps otherwise)
-    if (p->storage <= LB_STORE_F32 && p->kernel != LB_KERNEL_TWOPASS && p->model == LB_MODEL_COLOUR_GRADIENT)
+    // phase sums of the one-read step (unless two passes are asked for; an
+    // upper bound for lattices the automatic choice steps otherwise)
+    if (p->kernel != LB_KERNEL_TWOPASS && p->model == LB_MODEL_COLOUR_GRADIENT)
         b += 2 * part_reals<kTX>(p->nx, p->ny, p->nz) * real;
+    // a 16-bit lattice's raw FP32 initial state, kept from lb_init_fields
+    if (p->storage >= LB_STORE_F16) b += pop_bytes(LB_STORE_F32, N);
     return (int64_t)b;
 }
 

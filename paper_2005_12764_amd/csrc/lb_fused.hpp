@@ -44,13 +44,15 @@ struct PhiRing {
 };
 
 // Ring of 3 planes of 16-bit-storage records (2 x f4 per site), tile plus one
-// site around it.
+// site around it; each plane holds the first f4 of every site, then the
+// second (consecutive lanes read consecutive 16-byte words: no bank conflicts).
 template <int TX>
 struct RecRing {
     static constexpr int LX = TX + 2;
     f4* base;
     int LY;
     __device__ __forceinline__ f4* plane(int slot) const { return base + (size_t)slot * LY * LX * 2; }
+    __device__ __forceinline__ int half() const { return LY * LX; }
 };
 
 template <typename R, int TX, int H>
@@ -76,8 +78,8 @@ __device__ __forceinline__ void load_rec_plane(const Geom& g, const Src& src, co
         const size_t s = (size_t)site_of(g, xx, yy, zz);
         const f4 a = *reinterpret_cast<const f4*>(src.rec + 8 * s);
         const f4 b = *reinterpret_cast<const f4*>(src.rec + 8 * s + 4);
-        dstp[2 * k] = a;
-        dstp[2 * k + 1] = b;
+        dstp[k] = a;
+        dstp[rr.half() + k] = b;
     }
 }
 
@@ -186,7 +188,7 @@ __device__ __forceinline__ void fused_tile(const Geom& g, const Src& src, const 
                 if constexpr (Src::ring) {
                     const f4* const planes[3] = {rr.plane((cz - za) % 3), rr.plane((cz - za + 1) % 3),
                                                  rr.plane((cz - za + 2) % 3)};
-                    src.pull_ring(g, s, x, y, cz, t, d, planes, ty + 1, tx + 1, RecRing<TX>::LX);
+                    src.pull_ring(g, s, x, y, cz, t, d, planes, ty + 1, tx + 1, RecRing<TX>::LX, rr.half());
                 } else {
                     src.pull(g, s, x, y, cz, t, d);
                 }
@@ -227,7 +229,7 @@ __device__ __forceinline__ void phase_tile(const Geom& g, const Src& src, R* __r
                     if (x >= g.nx || y >= g.ny) continue;
                     const int s = site_of(g, x, y, cz);
                     R t[Q], d[Q];
-                    src.pull_ring(g, s, x, y, cz, t, d, planes, ty + 1, tx + 1, RecRing<TX>::LX);
+                    src.pull_ring(g, s, x, y, cz, t, d, planes, ty + 1, tx + 1, RecRing<TX>::LX, rr.half());
                     phi[s] = phase_of(t, d);
                 }
             }

@@ -63,6 +63,10 @@ int launch_step(const LatticeView& v, int kernel, const StepEvents* t = nullptr)
 // stream fin into fout, gathering the next state's own phase sums.
 template <typename T>
 int launch_lean(const LatticeView& v, const T* fin, T* fout, const Coeffs<T>& c, const FusedShape& fs);
+// The same for 16-bit moment-split storage (lb_lean16.hip).
+template <typename H>
+int launch_lean_split(const LatticeView& v, const SplitPop<H>& src, const SplitPop<H>& dst, const Coeffs<float>& c,
+                      const FusedShape& fs);
 int launch_init(const LatticeView& v, const void* rr, const void* rb, const void* u, int dtype);
 int launch_import(const LatticeView& v, const void* f, int dtype);
 int launch_export(const LatticeView& v, void* out, int dtype);

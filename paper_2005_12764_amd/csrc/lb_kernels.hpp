@@ -244,12 +244,16 @@ __device__ __forceinline__ float cdot(int i, float sg, float ax, float ay, float
 }
 
 // 16-bit moment-split storage.  Per site, 8 FP32 values rec[N][8] (two
-// 16-byte vectors per site): density - 1,
-// velocity (3), red fraction, recolouring vector (3) of the post-collision
-// state; per direction dev[19][N]: the total post-collision population minus
-// its equilibrium rho f^eq_unit(u), times `scale`, in 16 bits.  The red part
-// of direction i is x_r f*_i + w_i (c_i . v)/|c_i|, which is exactly the form
-// recolouring produces, so colour is carried in FP32.  MW as for RawPop.
+// 16-byte vectors per site) of the post-collision state: density - 1, the
+// momentum term J = 3 (j + F) of the equilibrium (3), the phase
+// phi = x_r - x_b and the recolouring vector (3); per direction dev[19][N]:
+// the total post-collision population's deviation t_i from the reference
+// w_i (drho + c_i . J) -- the equilibrium to first order in the velocity --
+// times `scale`, in 16 bits (the second-order part of the equilibrium, of
+// order u^2, is carried by the deviation with the non-equilibrium part).  The
+// colour difference of direction i is phi (w_i + t_i) + 2 w_i (c_i . v)/|c_i|,
+// exactly the form recolouring produces, so colour is carried in FP32.  MW as
+// for RawPop.
 template <typename H, bool MW = false>
 struct SplitPop {
     float* rec;
@@ -257,26 +261,22 @@ struct SplitPop {
     size_t N;
     float scale, inv_scale;
 
-    // Equilibrium excess of direction i (read as d = i, sg = 1, or as its
+    // Reference excess of direction i (read as d = i, sg = 1, or as its
     // opposite after a bounce-back, sg = -1) from the source record ra:
-    // X = drho + rho q(u), so that f*_i - w_i = w_i X + deviation.  Fused
-    // multiply-adds are written out so that every reading of a stored value,
-    // and the store's own reading, rounds the same way.
+    // X = drho + c_i . J, so that f*_i - w_i = w_i X + deviation.  The
+    // arithmetic is written out term by term so that every reading of a
+    // stored value, and the store's own reading, rounds the same way.
     static __device__ __forceinline__ float excess(int i, float sg, const f4& ra) {
-        const float drho = ra.x, ux = ra.y, uy = ra.z, uz = ra.w;
-        const float cu = cdot(i, sg, ux, uy, uz);
-        const float uu = __builtin_fmaf(ux, ux, __builtin_fmaf(uy, uy, uz * uz));
-        const float q = __builtin_fmaf(cu, __builtin_fmaf(4.5f, cu, 3.0f), -1.5f * uu);
-        return __builtin_fmaf(1.0f + drho, q, drho);
+        return ra.x + cdot(i, sg, ra.y, ra.z, ra.w);
     }
     // Shifted variables t_i = f*_i - w_i and d_i = f^r_i - f^b_i from the
     // excess X, the 16-bit deviation and the colour part of the record rb.
     __device__ __forceinline__ void finish(int i, float sg, float X, const f4& rb, H dv16, float& tt,
                                            float& dd) const {
         const float w = weight<float>(i);
-        tt = __builtin_fmaf(w, X, Half<H>::to_f(dv16) * inv_scale);
+        tt = __builtin_fmaf(Half<H>::to_f(dv16), inv_scale, w * X);
         const float cv = cdot(i, sg, rb.y, rb.z, rb.w);
-        dd = __builtin_fmaf(2.0f * rb.x - 1.0f, w + tt, (2.0f * w * inv_clen<float>(i)) * cv);
+        dd = __builtin_fmaf(rb.x, w + tt, (2.0f * w * inv_clen<float>(i)) * cv);
     }
     template <typename R>
     __device__ __forceinline__ void decode(int i, int d, const f4& ra, const f4& rb, H dv16, R& t_i,
@@ -314,9 +314,9 @@ struct SplitPop {
     }
 
     // Moving-wall terms of the reflected directions, shared by the site's own
-    // post-collision red fraction xr (from its record).
+    // post-collision phase phi (from its record): add x_r - add x_b.
     template <typename R>
-    __device__ void add_wall_terms(const Geom& g, int s, int x, int y, int z, float xr, R (&t)[Q],
+    __device__ void add_wall_terms(const Geom& g, int s, int x, int y, int z, float phi, R (&t)[Q],
                                    R (&d)[Q]) const {
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
@@ -325,7 +325,7 @@ struct SplitPop {
             if (dir == i) continue;
             const R add = wall_term<R>(g, i, x, y, z);
             t[i] += add;
-            d[i] += add * (R(2) * R(xr) - R(1));
+            d[i] += add * R(phi);
         }
     }
 
@@ -336,7 +336,7 @@ struct SplitPop {
     template <typename R>
     __device__ __forceinline__ void pull_ring(const Geom& g, int s, int x, int y, int z, R (&t)[Q],
                                               R (&d_)[Q], const f4* const (&ring)[3], int ly, int lx,
-                                              int LXR) const {
+                                              int LXR, int half) const {
         using L = Lattice;
         const Nbr nb = nbr_of(g, s, x, y, z);
 #pragma unroll
@@ -346,11 +346,11 @@ struct SplitPop {
             const bool bb = (d != i);
             const f4* pl = bb ? ring[1] : ring[1 - L::cz[i]];
             const int pos = bb ? (ly * LXR + lx) : ((ly - L::cy[i]) * LXR + lx - L::cx[i]);
-            decode<R>(i, d, pl[2 * pos], pl[2 * pos + 1], dev[(size_t)d * N + src], t[i], d_[i]);
+            decode<R>(i, d, pl[pos], pl[half + pos], dev[(size_t)d * N + src], t[i], d_[i]);
         }
         if constexpr (MW) {
-            const float xr_own = ring[1][2 * (ly * LXR + lx) + 1].x;
-            if (g.moving) add_wall_terms<R>(g, s, x, y, z, xr_own, t, d_);
+            const float phi_own = ring[1][half + ly * LXR + lx].x;
+            if (g.moving) add_wall_terms<R>(g, s, x, y, z, phi_own, t, d_);
         }
     }
 
@@ -368,8 +368,8 @@ struct SplitPop {
     // Store, and replace t, d by the values a later pull decodes (exactly).
     template <typename R>
     __device__ __forceinline__ void store_as_read(int s, R (&t)[Q], R (&d)[Q], const SiteTotals<R>& tot) const {
-        const f4 ra = {float(tot.drho), float(tot.ux), float(tot.uy), float(tot.uz)};
-        const f4 rb = {float(tot.xr), float(tot.vx), float(tot.vy), float(tot.vz)};
+        const f4 ra = {float(tot.drho), float(tot.jx), float(tot.jy), float(tot.jz)};
+        const f4 rb = {float(tot.phi), float(tot.vx), float(tot.vy), float(tot.vz)};
         __builtin_nontemporal_store(ra, reinterpret_cast<f4*>(rec + 8 * (size_t)s));
         __builtin_nontemporal_store(rb, reinterpret_cast<f4*>(rec + 8 * (size_t)s + 4));
 #pragma unroll

@@ -123,7 +123,11 @@ int single_h(const LatticeView& v, const Src& src, const Dst& dst, const Coeffs<
     if constexpr (!Src::ring && !Dst::ring) {
         // raw storage: the lean tile kernel
         return launch_lean<R>(v, src.f, dst.f, c, fs);
+    } else if constexpr (Src::ring && Dst::ring) {
+        // 16-bit moment-split storage: the lean tile kernel with the record ring
+        return launch_lean_split(v, src, dst, c, fs);
     } else {
+        // the first step of a 16-bit lattice, from its raw FP32 initial state
         const size_t lds = tile_lds(*v.p, TILE_SINGLE, TY);
         auto kern = single_kernel<R, Src, Dst, kTX, TY, H>;
         if (lds > 65536) {
@@ -289,8 +293,7 @@ size_t tile_lds(const lb_params& p, int kind, int TY) {
                   // (raw storage: rows padded by a zero at both ends), running x-face sums
                   // of the edge lanes
             return ((phi + 15) & ~size_t(15)) + (split ? rec : 0) +
-                   (size_t)2 * kXchDirs * (split ? kTX : kTX + 2) * TY * real_size(p) +
-                   (size_t)2 * 3 * TY * 2 * real_size(p);
+                   (size_t)2 * kXchDirs * (kTX + 2) * TY * real_size(p) + (size_t)2 * 3 * TY * 2 * real_size(p);
     }
 }
 
@@ -302,10 +305,11 @@ int tile_rows(const lb_params& p, int kind) {
         // workgroups, one per CU: the autotuner's choice at 256^3) when they
         // split into whole rounds of 256 such workgroups, so that no CU idles
         // (measured: 384^3 with 144 of them ran 24 % slower than with 8 rows);
-        // other raw storage and other FP32 lattices take 8; 16-bit storage
-        // takes 4 (its record ring makes 8 rows a one-workgroup-per-CU tile)
+        // other lattices take 8 (16-bit storage too: with its record ring that
+        // is one workgroup of 8 waves per CU, measured faster than two
+        // workgroups of 4 rows)
         const int set = tile_setting(TILE_SINGLE, p.storage).ty;
-        int dflt = split_storage(p) ? kSingleTYSmall : kSingleTY;
+        int dflt = kSingleTY;
         if (p.storage == LB_STORE_F32 && set <= 0 && (size_t)p.nx * p.ny * p.nz >= ((size_t)1 << 23)) {
             const int tiles = ((p.nx + kTX - 1) / kTX) * ((p.ny + kSingleTYLarge - 1) / kSingleTYLarge);
             const int want_chunks = std::max(1, 256 / tiles);
@@ -345,8 +349,12 @@ FusedShape tile_shape(const lb_params& p, int kind, int target_blocks) {
     // the autotuner's choices for the 256^3 emulsion on MI355X: 16-plane chunks
     // for the 16-bit phase pass and the raw-storage two-pass collide
     if (tz <= 0 && (kind == TILE_PHASE || (kind == TILE_COLLIDE && !split_storage(p)))) tz = 16;
-    // 16-row one-read tiles are 1024-thread workgroups, one per CU: aim for 256
-    if (kind == TILE_SINGLE && fs.TY == kSingleTYLarge) target_blocks = 256;
+    // one-read tiles that fill a CU alone -- 16-row tiles (1024 threads) and
+    // 16-bit storage's 8-row tiles (their LDS rings) -- aim for one round of
+    // 256 workgroups (deep chunks: fewer halo planes and face sites; measured
+    // at 256^3: fp16 1.31 ms/step with 32-plane chunks, 1.23 ms with 128)
+    if (kind == TILE_SINGLE && (fs.TY == kSingleTYLarge || (split_storage(p) && fs.TY == kSingleTY)))
+        target_blocks = 256;
     if (tz <= 0) {
         // aim for target_blocks workgroups, keeping chunks a few halos deep
         const int H = kind == TILE_PHASE ? 1 : tile_halo(p);
@@ -363,18 +371,16 @@ int choose_kernel(const lb_params& p) {
     const bool fits = tile_rows(p, TILE_SINGLE) > 0;
     if (p.kernel == LB_KERNEL_TWOPASS) return LB_KERNEL_TWOPASS;
     if (p.kernel == LB_KERNEL_FUSED) return fits ? LB_KERNEL_FUSED : -1;
-    // automatic: the one-read step for raw storage (measured faster than two
-    // passes); 16-bit storage and lattices with moving walls take two passes
-    // (the 16-bit collide is bound by its decode arithmetic, where the
-    // one-read step's extra work does not pay; moving walls need wall terms
-    // the one-read step does not carry)
+    // automatic: the one-read step (measured faster than two passes for raw
+    // and 16-bit storage); lattices with moving walls take two passes (they
+    // need wall terms the one-read step does not carry), and so do the
+    // Shan-Chen model and lattices too large for 32-bit buffer offsets
     bool moving = false;
     for (int f = 0; f < 6; ++f)
         for (int k = 0; k < 3; ++k) moving |= p.bc[f / 2] != 0 && p.wall_velocity[f][k] != 0.0;
     // (the one-read step's 32-bit byte offsets need 10 x sites x value size < 2^32)
     const bool small = (uint64_t)kResArrays * real_size(p) * (uint64_t)p.nx * p.ny * p.nz < ((uint64_t)1 << 32);
-    if (split_storage(p) || moving || !fits || !small || p.model != LB_MODEL_COLOUR_GRADIENT)
-        return LB_KERNEL_TWOPASS;
+    if (moving || !fits || !small || p.model != LB_MODEL_COLOUR_GRADIENT) return LB_KERNEL_TWOPASS;
     return LB_KERNEL_FUSED;
 }
 

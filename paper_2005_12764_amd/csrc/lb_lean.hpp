@@ -83,15 +83,6 @@ __device__ __forceinline__ double from_right(double v) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-// Exchange rows in LDS: per tile row, kXchDirs x 2 values (w_i + t_i, d_i)
-// of the directions with c_y != 0, each a row of 64 lanes with a zero pad
-// before and after it.
-constexpr int kLeanRowPad = kTX + 2;
-template <typename R, int TY>
-__host__ __device__ constexpr size_t lean_xch_bytes() {
-    return (size_t)TY * 2 * kXchDirs * kLeanRowPad * sizeof(R);
-}
-
 // Upstream row (scalar): element offset (z*ny + y)*nx of the row a population
 // with velocity (., cy, cz) arriving in row (y, z) comes from, with the
 // periodic wrap.  W: the lattice may have walls; `bb` is then set when that
@@ -104,6 +95,236 @@ __device__ __forceinline__ unsigned upstream_row(const Geom& g, int y, int z, in
     zs = zs < 0 ? zs + g.nz : (zs >= g.nz ? zs - g.nz : zs);
     bb = W && ((g.wy && out_y) || (g.wz && out_z));
     return (unsigned)((zs * g.ny + ys) * g.nx);
+}
+
+// Plane and lane context of the pulls and stores of a lean tile.
+struct LeanPlane {
+    unsigned Np;       // sites N, re-read each plane (keeps array offsets out of loop-invariant registers)
+    unsigned own_row;  // (cz ny + yc) nx, the site's row
+    int yc, cz;        // the site's (clamped) row and its plane
+    int rs[3];         // record-ring slots of planes cz - 1, cz, cz + 1 (16-bit storage)
+};
+struct LeanLane {
+    unsigned cx0, cxm, cxp;   // columns x, x - 1, x + 1 (periodic wrap; beyond an x wall x itself)
+    bool wall_xlo, wall_xhi;  // an x wall lies beyond this lane's site
+    int lane, ty;
+};
+
+// Raw storage: t_i and d_i in 2 Q arrays of T.  Pulls read each array at the
+// upstream row (scalar offset) and column (per lane); stores write in place.
+template <typename T>
+struct LeanRaw {
+    using R = T;
+    static constexpr bool split = false;
+    const T* fin;
+    T* fout;
+    __host__ __device__ static constexpr size_t ring_bytes(int) { return 0; }
+    __device__ __forceinline__ void stage(const Geom&, int, int, int, int, int, int) const {}
+
+    template <bool W>
+    __device__ __forceinline__ void pull(const Geom& g, const LeanPlane& P, const LeanLane& ln, R (&t)[Q],
+                                         R (&d)[Q]) const {
+        using L = Lattice;
+        const T* fin_p = fin;
+        asm volatile("" : "+s"(fin_p));  // resources rebuilt each plane (short-lived scalar registers)
+        const PopRes<T> fi(fin_p, P.Np);
+        constexpr unsigned SZ = (unsigned)sizeof(T);
+        const unsigned bx0 = ln.cx0 * SZ, bxm = ln.cxm * SZ, bxp = ln.cxp * SZ;
+        // byte offset of array a (0..2Q-1) at element e within its resource
+        auto soff = [&](int a, unsigned e) { return ((unsigned)(a % kResArrays) * P.Np + e) * SZ; };
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            bool bb;
+            const unsigned row = upstream_row<W>(g, P.yc, P.cz, L::cy[i], L::cz[i], bb);
+            const unsigned col = L::cx[i] > 0 ? bxm : (L::cx[i] < 0 ? bxp : bx0);
+            if (W && bb) {
+                // a bounce-back reads the site itself in the opposite direction
+                const int o = L::opp[i];
+                t[i] = res_load(R(0), fi.r[o / kResArrays], bx0, soff(o, P.own_row));
+                d[i] = res_load(R(0), fi.r[(Q + o) / kResArrays], bx0, soff(Q + o, P.own_row));
+            } else {
+                t[i] = res_load(R(0), fi.r[i / kResArrays], col, soff(i, row));
+                d[i] = res_load(R(0), fi.r[(Q + i) / kResArrays], col, soff(Q + i, row));
+            }
+        }
+        if constexpr (W) {
+            if (ln.wall_xlo || ln.wall_xhi) {
+#pragma unroll
+                for (int i = 1; i < Q; ++i) {
+                    if (!((L::cx[i] > 0 && ln.wall_xlo) || (L::cx[i] < 0 && ln.wall_xhi))) continue;
+                    const int o = L::opp[i];
+                    t[i] = res_load(R(0), fi.r[o / kResArrays], bx0, soff(o, P.own_row));
+                    d[i] = res_load(R(0), fi.r[(Q + o) / kResArrays], bx0, soff(Q + o, P.own_row));
+                }
+            }
+        }
+    }
+
+    // Store, and keep in t, d the values a later pull reads.
+    __device__ __forceinline__ void store(const Geom&, const LeanPlane& P, const LeanLane& ln, R (&t)[Q],
+                                          R (&d)[Q], const SiteTotals<R>&, bool site_in) const {
+        if (site_in) {
+            T* fout_p = fout;
+            asm volatile("" : "+s"(fout_p));
+            const PopRes<T> fo(fout_p, P.Np);
+            constexpr unsigned SZ = (unsigned)sizeof(T);
+            auto soff = [&](int a, unsigned e) { return ((unsigned)(a % kResArrays) * P.Np + e) * SZ; };
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                res_store(T(t[i]), fo.r[i / kResArrays], ln.cx0 * SZ, soff(i, P.own_row));
+                res_store(T(d[i]), fo.r[(Q + i) / kResArrays], ln.cx0 * SZ, soff(Q + i, P.own_row));
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            t[i] = R(T(t[i]));
+            d[i] = R(T(d[i]));
+        }
+    }
+};
+
+// 16-bit moment-split storage (the codec of SplitPop): per site an FP32
+// record of 8 values, per direction a 16-bit deviation.  The records of
+// planes cz - 1, cz, cz + 1 (tile plus one site) sit in an LDS ring, staged a
+// plane ahead, so a pull reads its source record from LDS and only the 16-bit
+// deviation from memory (scalar row offset, per-lane column).
+__device__ __forceinline__ f4 res_load4(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    return __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+__device__ __forceinline__ void res_store4(f4 v, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    using V = decltype(__builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(V, v), r, voff, soff, 2);
+}
+template <typename H>
+struct LeanSplit {
+    using R = float;
+    static constexpr bool split = true;
+    static constexpr int LXR = kTX + 2;  // ring row: the tile's 64 columns and one on each side
+    const float* rin;                   // records [N][8] of the current state
+    const H* din;                       // deviations [Q][N] of the current state
+    float* rout;                        // the same of the next state
+    H* dout;
+    SplitPop<H> codec;                  // scale and the record arithmetic
+    f4* ring;                           // LDS: 3 planes x 2 halves x (TY + 2) rows x LXR sites, f4
+    int TY;
+    __host__ __device__ static constexpr size_t ring_bytes(int ty) {
+        return (size_t)3 * (ty + 2) * LXR * 2 * sizeof(f4);
+    }
+    // a plane holds the first f4 of every site, then (half() later) the second:
+    // consecutive lanes read consecutive 16-byte words, free of bank conflicts
+    __device__ __forceinline__ f4* plane(int slot) const { return ring + (size_t)slot * (TY + 2) * LXR * 2; }
+    __device__ __forceinline__ int half() const { return (TY + 2) * LXR; }
+    __device__ __forceinline__ __amdgpu_buffer_rsrc_t rec_res(const float* p, unsigned N) const {
+        asm volatile("" : "+s"(p));
+        return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(p), 0, (int)(N * 32u), (int)kRsrcWord3);
+    }
+    __device__ __forceinline__ __amdgpu_buffer_rsrc_t dev_res(const H* p, unsigned N) const {
+        asm volatile("" : "+s"(p));
+        return __builtin_amdgcn_make_buffer_rsrc(const_cast<H*>(p), 0, (int)(Q * N * 2u), (int)kRsrcWord3);
+    }
+
+    // Records of plane q, rows y0 - 1 .. y0 + TY and columns x0 - 1 .. x0 + 64
+    // (periodic wrap or mirror images beyond walls), into a ring slot.
+    __device__ __forceinline__ void stage(const Geom& g, int q, int slot, int x0, int y0, int ty, int lane) const {
+        const int zz = halo_coord(q, g.nz, g.wz);
+        const unsigned ca = (unsigned)halo_coord(x0 - 1 + lane, g.nx, g.wx) * 32u;
+        const unsigned cb = (unsigned)halo_coord(x0 - 1 + kTX + lane, g.nx, g.wx) * 32u;
+        const __amdgpu_buffer_rsrc_t rr = rec_res(rin, (unsigned)g.N);
+        f4* pl = plane(slot);
+        for (int r = ty; r < TY + 2; r += TY) {
+            const int yy = halo_coord(y0 - 1 + r, g.ny, g.wy);
+            const unsigned so = (unsigned)((zz * g.ny + yy) * g.nx) * 32u;
+            const f4 a0 = res_load4(rr, ca, so), a1 = res_load4(rr, ca + 16u, so);
+            pl[r * LXR + lane] = a0;
+            pl[half() + r * LXR + lane] = a1;
+            if (lane < 2) {
+                const f4 b0 = res_load4(rr, cb, so), b1 = res_load4(rr, cb + 16u, so);
+                pl[r * LXR + kTX + lane] = b0;
+                pl[half() + r * LXR + kTX + lane] = b1;
+            }
+        }
+    }
+
+    template <bool W>
+    __device__ __forceinline__ void pull(const Geom& g, const LeanPlane& P, const LeanLane& ln, R (&t)[Q],
+                                         R (&d)[Q]) const {
+        using L = Lattice;
+        const __amdgpu_buffer_rsrc_t dr = dev_res(din, P.Np);
+        const f4* pm = plane(P.rs[0]);
+        const f4* p0 = plane(P.rs[1]);
+        const f4* pp = plane(P.rs[2]);
+        const int own = (ln.ty + 1) * LXR + ln.lane + 1;
+        auto dv = [&](int a, unsigned col, unsigned row) {
+            return __builtin_bit_cast(H, __builtin_amdgcn_raw_buffer_load_b16(dr, col * 2u, ((unsigned)a * P.Np + row) * 2u, 0));
+        };
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            bool bb;
+            const unsigned row = upstream_row<W>(g, P.yc, P.cz, L::cy[i], L::cz[i], bb);
+            if (W && bb) {
+                const int o = L::opp[i];
+                codec.decode(i, o, p0[own], p0[half() + own], dv(o, ln.cx0, P.own_row), t[i], d[i]);
+            } else {
+                // the source (x - c_i) in plane cz - c_z: cz - 1 is pm, cz + 1 is pp
+                const f4* pl = L::cz[i] > 0 ? pm : (L::cz[i] < 0 ? pp : p0);
+                const int pos = own - L::cy[i] * LXR - L::cx[i];
+                const unsigned col = L::cx[i] > 0 ? ln.cxm : (L::cx[i] < 0 ? ln.cxp : ln.cx0);
+                codec.decode(i, i, pl[pos], pl[half() + pos], dv(i, col, row), t[i], d[i]);
+            }
+        }
+        if constexpr (W) {
+            if (ln.wall_xlo || ln.wall_xhi) {
+#pragma unroll
+                for (int i = 1; i < Q; ++i) {
+                    if (!((L::cx[i] > 0 && ln.wall_xlo) || (L::cx[i] < 0 && ln.wall_xhi))) continue;
+                    const int o = L::opp[i];
+                    codec.decode(i, o, p0[own], p0[half() + own], dv(o, ln.cx0, P.own_row), t[i], d[i]);
+                }
+            }
+        }
+    }
+
+    // Encode and store the record and the deviations, and keep in t, d the
+    // values a later pull decodes (exactly: the same codec arithmetic).
+    __device__ __forceinline__ void store(const Geom& g, const LeanPlane& P, const LeanLane& ln, R (&t)[Q],
+                                          R (&d)[Q], const SiteTotals<R>& tot, bool site_in) const {
+        const f4 ra = {tot.drho, tot.jx, tot.jy, tot.jz};
+        const f4 rb = {tot.phi, tot.vx, tot.vy, tot.vz};
+        H h[Q];
+        float X[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            X[i] = SplitPop<H>::excess(i, 1.0f, ra);
+            h[i] = Half<H>::from_f((t[i] - weight<float>(i) * X[i]) * codec.scale);
+        }
+        if (site_in) {
+            const __amdgpu_buffer_rsrc_t rr = rec_res(rout, P.Np);
+            const __amdgpu_buffer_rsrc_t dr = dev_res(dout, P.Np);
+            res_store4(ra, rr, ln.cx0 * 32u, P.own_row * 32u);
+            res_store4(rb, rr, ln.cx0 * 32u + 16u, P.own_row * 32u);
+#pragma unroll
+            for (int i = 0; i < Q; ++i)
+                __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, h[i]), dr, ln.cx0 * 2u,
+                                                      ((unsigned)i * P.Np + P.own_row) * 2u, 2);
+        }
+        (void)g;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            float tt, dd;
+            codec.finish(i, 1.0f, X[i], rb, h[i], tt, dd);
+            t[i] = tt;
+            d[i] = dd;
+        }
+    }
+};
+
+// Exchange rows in LDS: per tile row, kXchDirs x 2 values (w_i + t_i, d_i)
+// of the directions with c_y != 0, each a row of 64 lanes with a zero pad
+// before and after it.
+constexpr int kLeanRowPad = kTX + 2;
+template <typename R, int TY>
+__host__ __device__ constexpr size_t lean_xch_bytes() {
+    return (size_t)TY * 2 * kXchDirs * kLeanRowPad * sizeof(R);
 }
 
 // As xedge_rows, reading the exchange rows of the lean tile: the in-plane
@@ -136,20 +357,22 @@ __device__ __forceinline__ void lean_xedge_rows(const Geom& g, const R* __restri
 // planes [za, zb); blockDim.x == 64 * TY.  W: the lattice has walls (an
 // all-periodic lattice carries none of their tests; the lanes next to an x
 // wall take their bounce-backs from a second, masked pull).
-template <typename R, typename T, int TY, int H, bool W>
-__device__ __forceinline__ void lean_tile(const Geom& g, const T* fin, T* fout,
-                                          const Coeffs<R>& c, R* __restrict__ ringb, R* __restrict__ xch,
-                                          Part2<R>* __restrict__ vs, int x0, int y0, int za, int zb,
-                                          const R* __restrict__ phi_in, Part2<R>* __restrict__ part_out,
-                                          R* __restrict__ phi_out) {
+template <typename S, int TY, int H, bool W>
+__device__ __forceinline__ void lean_tile(const Geom& g, const S& st, const Coeffs<typename S::R>& c,
+                                          typename S::R* __restrict__ ringb, typename S::R* __restrict__ xch,
+                                          Part2<typename S::R>* __restrict__ vs, int x0, int y0, int za, int zb,
+                                          const typename S::R* __restrict__ phi_in,
+                                          Part2<typename S::R>* __restrict__ part_out,
+                                          typename S::R* __restrict__ phi_out) {
     using L = Lattice;
+    using R = typename S::R;
     constexpr int TX = kTX;
     constexpr int LX = TX + 2 * H;
     constexpr int NP = 2 * H + 1;
     constexpr int LY = TY + 2 * H;
     constexpr int PLANE = LY * LX;
     constexpr int XROW = 2 * kXchDirs * kLeanRowPad;  // exchange reals per tile row
-    const unsigned N = (unsigned)g.N;  // 10 N sizeof(T) < 2^32 (checked on the host)
+    const unsigned N = (unsigned)g.N;  // byte offsets within a resource < 2^32 (checked on the host)
     const int lane = threadIdx.x & 63;
     const int ty = wave_uniform(threadIdx.x >> 6);
     const int x = x0 + lane;
@@ -170,10 +393,7 @@ __device__ __forceinline__ void lean_tile(const Geom& g, const T* fin, T* fout,
     const unsigned cxm = (unsigned)(xc == 0 ? (WX ? 0 : g.nx - 1) : xc - 1);
     const unsigned cxp = (unsigned)(xc == g.nx - 1 ? (WX ? xc : 0) : xc + 1);
     const bool wall_xlo = WX && xc == 0, wall_xhi = WX && xc == g.nx - 1;
-    // the same as 32-bit byte offsets: a scalar base plus one of these is a
-    // global access with an SGPR base (no 64-bit address arithmetic per access)
-    const unsigned bx0 = cx0 * (unsigned)sizeof(T), bxm = cxm * (unsigned)sizeof(T),
-                   bxp = cxp * (unsigned)sizeof(T);
+    const LeanLane ln{cx0, cxm, cxp, wall_xlo, wall_xhi, lane, ty};
     // phase-ring columns of this lane: x0 - H + lane and x0 - H + 64 + lane
     const int ra = halo_coord(x0 - H + lane, g.nx, g.wx);
     const int rb = halo_coord(x0 - H + TX + lane, g.nx, g.wx);
@@ -224,6 +444,11 @@ __device__ __forceinline__ void lean_tile(const Geom& g, const T* fin, T* fout,
                 }
             }
         }
+        if constexpr (S::split) {
+            // records of plane p - H + 1, the cz + 1 of the plane collided below
+            const int qr = p - H + 1;
+            if (qr >= za - 1 && qr <= zb) st.stage(g, qr, (qr - (za - 1)) % 3, x0, y0, ty, lane);
+        }
         __syncthreads();
         if (p + 1 < zb + H) fetch(p + 1);
         const int cz = p - H;
@@ -235,43 +460,17 @@ __device__ __forceinline__ void lean_tile(const Geom& g, const T* fin, T* fout,
         // registers (which spill)
         unsigned Np = N;
         asm volatile("" : "+s"(Np));
-        // buffer resources rebuilt each plane (short-lived scalar registers)
-        const T* fin_p = fin;
-        T* fout_p = fout;
-        asm volatile("" : "+s"(fin_p), "+s"(fout_p));
-        const PopRes<T> fi(fin_p, Np), fo(fout_p, Np);
-        constexpr unsigned SZ = (unsigned)sizeof(T);
-        const unsigned own_row = (unsigned)((cz * g.ny + yc) * g.nx);
-        // byte offset of array a (0..2Q-1) at element e within its resource
-        auto soff = [&](int a, unsigned e) { return ((unsigned)(a % kResArrays) * Np + e) * SZ; };
-        // ---- pull (x, y, cz): row in the scalar offset, column per lane
+        LeanPlane P;
+        P.Np = Np;
+        P.own_row = (unsigned)((cz * g.ny + yc) * g.nx);
+        P.yc = yc;
+        P.cz = cz;
+        P.rs[0] = (cz - 1 - (za - 1)) % 3;
+        P.rs[1] = (cz - (za - 1)) % 3;
+        P.rs[2] = (cz + 1 - (za - 1)) % 3;
+        // ---- pull (x, y, cz)
         R t[Q], d[Q];
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            bool bb;
-            const unsigned row = upstream_row<W>(g, yc, cz, L::cy[i], L::cz[i], bb);
-            const unsigned col = L::cx[i] > 0 ? bxm : (L::cx[i] < 0 ? bxp : bx0);
-            if (W && bb) {
-                // a bounce-back reads the site itself in the opposite direction
-                const int o = L::opp[i];
-                t[i] = res_load(R(0), fi.r[o / kResArrays], bx0, soff(o, own_row));
-                d[i] = res_load(R(0), fi.r[(Q + o) / kResArrays], bx0, soff(Q + o, own_row));
-            } else {
-                t[i] = res_load(R(0), fi.r[i / kResArrays], col, soff(i, row));
-                d[i] = res_load(R(0), fi.r[(Q + i) / kResArrays], col, soff(Q + i, row));
-            }
-        }
-        if constexpr (W) {
-            if (wall_xlo || wall_xhi) {
-#pragma unroll
-                for (int i = 1; i < Q; ++i) {
-                    if (!((L::cx[i] > 0 && wall_xlo) || (L::cx[i] < 0 && wall_xhi))) continue;
-                    const int o = L::opp[i];
-                    t[i] = res_load(R(0), fi.r[o / kResArrays], bx0, soff(o, own_row));
-                    d[i] = res_load(R(0), fi.r[(Q + o) / kResArrays], bx0, soff(Q + o, own_row));
-                }
-            }
-        }
+        st.template pull<W>(g, P, ln, t, d);
         // ---- colour gradient from the ring: base at (ty + H - 1, lane + H - 1)
         R gx, gy, gz;
         {
@@ -297,20 +496,10 @@ __device__ __forceinline__ void lean_tile(const Geom& g, const T* fin, T* fout,
             PhiRing<R, TX, H> ring{ringb, LY};
             ring_near_contact<R, TX, H>(g, ring, s0, xc, yc, cz, ty + H, lane + H, gx, gy, gz, c, Fx, Fy, Fz);
         }
-        collide<R>(t, d, gx, gy, gz, Fx, Fy, Fz, c, nullptr);
+        SiteTotals<R> tot;
+        collide<R>(t, d, gx, gy, gz, Fx, Fy, Fz, c, &tot);
         // ---- store (x, y, cz) and keep the values a later pull reads
-        if (row_in && xin) {
-#pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                res_store(T(t[i]), fo.r[i / kResArrays], bx0, soff(i, own_row));
-                res_store(T(d[i]), fo.r[(Q + i) / kResArrays], bx0, soff(Q + i, own_row));
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            t[i] = R(T(t[i]));
-            d[i] = R(T(d[i]));
-        }
+        st.store(g, P, ln, t, d, tot, row_in && xin);
         if (ragged) {
             // lanes beyond the lattice hand nothing to their neighbours
             if (!xin) {
@@ -438,20 +627,34 @@ __device__ __forceinline__ void lean_tile(const Geom& g, const T* fin, T* fout,
     }
 }
 
-template <typename R, typename T, int TY, int H, bool W>
-__global__ __launch_bounds__(kTX * TY) void lean_kernel(Geom g, const T* __restrict__ fin, T* __restrict__ fout,
-                                                       Coeffs<R> c, FusedShape fs,
-                                                       const Part2<R>* __restrict__ part_in,
-                                                       Part2<R>* __restrict__ part_out) {
+// LDS of a lean tile: phase-field ring, record ring (16-bit storage),
+// exchange rows, x-face running sums.
+template <typename S, int TY, int H>
+__host__ __device__ constexpr size_t lean_lds_bytes() {
+    using R = typename S::R;
+    return ((phi_ring_bytes<R, kTX, H>(TY) + 15) & ~size_t(15)) + S::ring_bytes(TY) + lean_xch_bytes<R, TY>() +
+           (size_t)2 * 3 * TY * sizeof(Part2<R>);
+}
+
+template <typename S, int TY, int H, bool W>
+__global__ __launch_bounds__(kTX * TY) void lean_kernel(Geom g, S st, Coeffs<typename S::R> c, FusedShape fs,
+                                                       const Part2<typename S::R>* __restrict__ part_in,
+                                                       Part2<typename S::R>* __restrict__ part_out) {
+    using R = typename S::R;
     extern __shared__ unsigned char lds_raw[];
     R* ringb = reinterpret_cast<R*>(lds_raw);
-    const size_t off = (phi_ring_bytes<R, kTX, H>(TY) + 15) & ~size_t(15);
+    size_t off = (phi_ring_bytes<R, kTX, H>(TY) + 15) & ~size_t(15);
+    if constexpr (S::split) {
+        st.ring = reinterpret_cast<f4*>(lds_raw + off);
+        st.TY = TY;
+    }
+    off += S::ring_bytes(TY);
     R* xch = reinterpret_cast<R*>(lds_raw + off);
     Part2<R>* vs = reinterpret_cast<Part2<R>*>(lds_raw + off + lean_xch_bytes<R, TY>());
     int x0, y0, za, zb;
     tile_of_block(fs, kTX, g.nz, x0, y0, za, zb);
-    lean_tile<R, T, TY, H, W>(g, fin, fout, c, ringb, xch, vs, x0, y0, za, zb,
-                               phi_of<kTX>(const_cast<Part2<R>*>(part_in), g), part_out, phi_of<kTX>(part_out, g));
+    lean_tile<S, TY, H, W>(g, st, c, ringb, xch, vs, x0, y0, za, zb,
+                           phi_of<kTX>(const_cast<Part2<R>*>(part_in), g), part_out, phi_of<kTX>(part_out, g));
 }
 
 }  // namespace lbm

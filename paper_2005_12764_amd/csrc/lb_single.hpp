@@ -467,7 +467,7 @@ __device__ __forceinline__ void single_tile(const Geom& g, const Src& src, const
                 if constexpr (Src::ring) {
                     const f4* const planes[3] = {rr.plane((cz - za) % 3), rr.plane((cz - za + 1) % 3),
                                                  rr.plane((cz - za + 2) % 3)};
-                    src.pull_ring(g, s, x, y, cz, t, d, planes, ty + 1, tx + 1, RecRing<TX>::LX);
+                    src.pull_ring(g, s, x, y, cz, t, d, planes, ty + 1, tx + 1, RecRing<TX>::LX, rr.half());
                 } else {
                     src.pull(g, s, x, y, cz, t, d);
                 }

@@ -62,12 +62,12 @@ def test_footprint_accounts_for_storage():
     f16 = lb.lb_footprint_bytes(dict(p, storage=W.F16))
     f64 = lb.lb_footprint_bytes(dict(p, storage=W.F64))
     N = 64 ** 3
-    # two population buffers, the phase field, and for raw storage the two
-    # phase-sum buffers of the one-read step: N own sums plus the x-face sums
-    # of the one 64-wide tile column (2 faces x 64 x 64 sites), in pairs, and
-    # the phase field of the state
+    # two population buffers, the phase field, and the two phase-sum buffers
+    # of the one-read step: N own sums plus the x-face sums of the one 64-wide
+    # tile column (2 faces x 64 x 64 sites), in pairs, and the phase field of
+    # the state; a 16-bit lattice also keeps its raw FP32 initial state
     reals = 2 * (N + 2 * 64 * 64) + N
     assert f32 == 2 * 2 * 19 * 4 * N + 4 * N + 2 * 4 * reals
     assert f64 == 2 * 2 * 19 * 8 * N + 8 * N + 2 * 8 * reals
-    assert f16 == 2 * (8 * 4 + 19 * 2) * N + 4 * N
+    assert f16 == 2 * (8 * 4 + 19 * 2) * N + 4 * N + 2 * 4 * reals + 2 * 19 * 4 * N
     assert lb.lb_footprint_bytes(dict(p, kernel=lb.KERNEL_TWOPASS)) == 2 * 2 * 19 * 4 * N + 4 * N
