@@ -7,7 +7,8 @@
 // as for the colour gradient), averaged with phi over blocks of b x b x b
 // sites.
 //
-// One workgroup covers 64 columns x 8 rows and marches a chunk of planes,
+// One workgroup covers 64 columns x 8 rows and marches a chunk of planes
+// (a one-dimensional grid of tiles x chunks, mapped to XCDs in runs),
 // the phase field of four planes (tile plus a one-site halo) in an LDS ring,
 // so each value is read from HBM about once.  Each thread sums its column's
 // seven values over the b planes of a block layer; at the end of a layer the
@@ -31,7 +32,16 @@ __global__ __launch_bounds__(64 * kKortewegRows) void korteweg_kernel(Geom g, co
     __shared__ R ring[NP * LY * LX];
     __shared__ R acc[TY * 64 * 7];  // [row][block column][value]
     const int lane = threadIdx.x & 63, row = threadIdx.x >> 6;
-    const int x0 = blockIdx.x * 64, y0 = blockIdx.y * TY, za = blockIdx.z * kKortewegChunk;
+    // tile of this workgroup: workgroups are dealt round-robin to the 8 XCDs,
+    // so the map gives each XCD a contiguous run of tiles (x fastest, then y,
+    // then chunks); neighbouring tiles then share their halo rows and columns
+    // in one L2 instead of fetching them from HBM twice
+    const int tx = (g.nx + 63) / 64, tyn = (g.ny + TY - 1) / TY;
+    const int nb = (int)gridDim.x;
+    int blk = (int)blockIdx.x;
+    if ((nb & 7) == 0) blk = (blk & 7) * (nb >> 3) + (blk >> 3);
+    const int tile = blk % (tx * tyn), chunk = blk / (tx * tyn);
+    const int x0 = (tile % tx) * 64, y0 = (tile / tx) * TY, za = chunk * kKortewegChunk;
     const int zb = min(za + kKortewegChunk, g.nz);
     const int x = x0 + lane, y = y0 + row;
     const bool active = x < g.nx && y < g.ny;

@@ -502,8 +502,8 @@ int launch_korteweg(const LatticeView& v, double lam, int b, void* kout, void* p
             rc = phase_pass<R>(v, src);
         }
         if (rc) return rc;
-        const dim3 grid((unsigned)((v.g.nx + 63) / 64), (unsigned)((v.g.ny + kKortewegRows - 1) / kKortewegRows),
-                        (unsigned)((v.g.nz + kKortewegChunk - 1) / kKortewegChunk));
+        const dim3 grid((unsigned)(((v.g.nx + 63) / 64) * ((v.g.ny + kKortewegRows - 1) / kKortewegRows) *
+                                   ((v.g.nz + kKortewegChunk - 1) / kKortewegChunk)));
         const dim3 block(64 * kKortewegRows);
         if (dtype == LB_DTYPE_F64)
             hipLaunchKernelGGL((korteweg_kernel<R, double>), grid, block, 0, v.stream, v.g, field, R(lam),
