@@ -79,7 +79,8 @@ extern "C" {
 #define LB_TILES_PHASE 0    /* phase-field pass of two-pass steps (16-bit storage) */
 #define LB_TILES_COLLIDE 1  /* collide-and-stream pass of two-pass steps */
 #define LB_TILES_ONE_READ 2 /* one-read step (rows 4, 8 or 16) */
-#define LB_TILES_BATCH 3    /* both passes of the batched step (rows 1, 2, 4 or 8) */
+#define LB_TILES_BATCH 3    /* tiles of the batched step (rows 4 or 8; other values: 8 at
+                               or above 8, else 4) */
 
 /* Interface model (lb_params.model). */
 #define LB_MODEL_COLOUR_GRADIENT 0 /* colour gradient: perturbation, recolouring, near contact */
@@ -238,9 +239,11 @@ const char* lb_last_error(void);
  * field before its next step); a batch takes it at lb_batch_create.  Rows
  * that do not fit the LDS budget are halved until they do.  For tools that
  * time tile shapes (the package's autotuner) and for callers applying their
- * results.  Results of two-pass and batched steps do not depend on the tile
- * shape; the one-read step's phase sums follow its tile boxes, so its results
- * move by rounding.  Not thread-safe against concurrent steps.
+ * results.  Results of two-pass steps do not depend on the tile shape; the
+ * one-read and batched steps' phase sums follow their tile boxes, so their
+ * results move by rounding (a batched job equals, bitwise, the same lattice
+ * stepped alone by the one-read step on the batch's tile boxes).  Not
+ * thread-safe against concurrent steps.
  * Errors: LB_EINVAL (unknown kind or storage, ty or tz out of range). */
 int lb_set_tiles(int32_t kind, int32_t storage, int32_t ty, int32_t tz);
 
@@ -249,8 +252,10 @@ int64_t lb_footprint_bytes(const lb_params* params);
 
 /* ------------------------------------------------------------------------
  * Batched form: many independent lattices (jobs) of uneven sizes and
- * parameters advanced together, one persistent kernel launch per pass over
- * every active job's tiles, replayed as a captured HIP graph of steps.
+ * parameters advanced together: each step is the one-read step of every
+ * active job in two persistent kernel launches (the face-site assembly of the
+ * phase field, then the collide-and-stream tiles), replayed as a captured HIP
+ * graph of steps.
  * All jobs of a batch share one storage type.  Job populations live in one
  * arena owned by the batch; admission fails with LB_ENOMEM when the arena has
  * no room, so the arena size is the HBM budget.
@@ -265,12 +270,16 @@ int lb_batch_create(int32_t max_jobs, int64_t arena_bytes, int32_t storage, int3
                     void* hip_stream, lb_batch_t** out);
 
 /* Admit one job that will run `steps` steps: validates params (storage must
- * equal the batch's; near-contact range at most 2), places it in the arena,
- * writes its initial state f^eq(rho_k, u) (a 16-bit job also takes its first
- * step here, from the raw FP32 initial state, so 16-bit jobs need steps >= 1;
- * each keeps its own deviation scale 2^scale_log2).  *slot gets its slot index.
- * LB_EINVAL for invalid parameters or a 16-bit job with steps = 0; LB_ENOMEM
- * when no slot or arena space is free.  Synchronises the stream. */
+ * equal the batch's; colour-gradient model; near-contact range at most 2; no
+ * moving walls), places it in the arena (two population buffers and two
+ * phase-sum buffers), writes its initial state f^eq(rho_k, u) and, when
+ * steps >= 1, takes its first step here with the single lattice's one-read
+ * step on the batch's tile boxes (a 16-bit job from its raw FP32 initial
+ * state, so 16-bit jobs need steps >= 1; each keeps its own deviation scale
+ * 2^scale_log2).  *slot gets its slot index.  LB_EINVAL for invalid
+ * parameters, a 16-bit job with steps = 0 or a job too large for the step's
+ * 32-bit buffer offsets; LB_ENOMEM when no slot or arena space is free.
+ * Synchronises the stream. */
 int lb_batch_add(lb_batch_t* b, const lb_params* params, const void* rho_r, const void* rho_b,
                  const void* u, int32_t dtype, int32_t on_device, int64_t steps, int32_t* slot);
 

@@ -35,7 +35,7 @@ CANDIDATES: Dict[int, List[Tuple[int, int]]] = {
     lb.TILES_ONE_READ: [(ty, tz) for ty in (4, 8, 16) for tz in (0, 16, 32, 64)],
     lb.TILES_COLLIDE: [(ty, tz) for ty in (2, 4, 8) for tz in (0, 16, 32, 64)],
     lb.TILES_PHASE: [(ty, tz) for ty in (4, 8, 16) for tz in (0, 16, 32, 64)],
-    lb.TILES_BATCH: [(ty, tz) for ty in (2, 4, 8) for tz in (8, 16, 32)],
+    lb.TILES_BATCH: [(ty, tz) for ty in (4, 8) for tz in (16, 32, 64)],
 }
 
 

@@ -1,14 +1,18 @@
 // lb_batch.hip -- many independent lattices (jobs) advanced together: each
-// step is one persistent phase-pass launch and one persistent collide-pass
-// launch, each walking a work list of (job, tile) items with the same tile
-// bodies as a single lattice; steps are replayed from a captured HIP graph.
+// step is one persistent assembly launch and one persistent tile launch, each
+// walking a work list of (job, item) pairs with the same code as the one-read
+// step of a single lattice (assemble_site, lean_tile), then a one-thread tick;
+// steps are replayed from a captured HIP graph.
 //
 // Each job has a window [first, last) of global steps.  A device counter holds
-// the global step; the step kernel reads it, skips jobs outside their window
-// and picks each job's ping-pong buffers from (step - first) parity, and a
-// one-thread kernel advances it.  The graph therefore never changes: admitting
-// or removing a job only rewrites the job table and the work list (ordered on
-// the batch stream), so jobs join and leave between replays.
+// the global step; the step kernels read it, skip jobs outside their window
+// and pick each job's ping-pong buffers (populations and phase sums) from
+// (step - first) parity, and the tick advances it.  The graph therefore never
+// changes: admitting or removing a job only rewrites the job table and the
+// work lists (ordered on the batch stream), so jobs join and leave between
+// replays.  Admission takes a job's first step on its own, through the single
+// lattice's one-read step with the batch's tile boxes, so that the job enters
+// the batch with the phase sums of its current state.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -22,46 +26,39 @@
 #include <vector>
 
 #include "lb.h"
-#include "lb_fused.hpp"
 #include "lb_internal.hpp"
+#include "lb_lean.hpp"
 
 using namespace lbm;
 
 namespace lbm {
 
-constexpr int kBatchTX = 64;
 constexpr int kBatchH = 3;   // halo for near-contact ranges up to 2
-constexpr int kBatchThreads = 256;
+constexpr int kAsmThreads = 256;
 
 template <typename R>
 struct BatchJob {
     Geom g;
     Coeffs<R> c;
     FusedShape fs;
-    void* buf[2];
-    void* phi;              // phase field of the job
+    FaceSet faces;          // face sites of the job's tile boxes (assembly)
+    void* buf[2];           // populations, ping-pong
+    void* part[2];          // phase sums and phase field of the state in buf[k]
     long long first, last;  // global-step window
     int active;
     int tiles;              // tiles_x * tiles_y
-    int fresh;              // the step at `first` reads an initial (not collided) state
     float scale;            // 16-bit deviation scale 2^scale_log2 of this job (1 otherwise)
 };
 
+// A tile item: block = tile + tiles * chunk.  An assembly item: block = index
+// of a run of kAsmThreads face sites.
 struct WorkItem {
     int slot;
-    int block;  // tile + tiles * chunk
+    int block;
 };
 
-template <typename S>
-__device__ __forceinline__ S storage_view(void* buf, size_t N, float scale);
-template <>
-__device__ __forceinline__ RawPop<float> storage_view<RawPop<float>>(void* buf, size_t N, float) {
-    return RawPop<float>{(float*)buf, N};
-}
-template <>
-__device__ __forceinline__ RawPop<double> storage_view<RawPop<double>>(void* buf, size_t N, float) {
-    return RawPop<double>{(double*)buf, N};
-}
+// Storage views of a job's buffers: the assembly's source view, and the
+// lean tile's policy from the source and destination buffers.
 template <typename H>
 __device__ __forceinline__ SplitPop<H> split_storage_view(void* buf, size_t N, float scale) {
     SplitPop<H> s;
@@ -72,20 +69,41 @@ __device__ __forceinline__ SplitPop<H> split_storage_view(void* buf, size_t N, f
     s.inv_scale = 1.0f / scale;
     return s;
 }
-template <>
-__device__ __forceinline__ SplitPop<__half> storage_view<SplitPop<__half>>(void* buf, size_t N, float scale) {
-    return split_storage_view<__half>(buf, N, scale);
-}
-template <>
-__device__ __forceinline__ SplitPop<__hip_bfloat16> storage_view<SplitPop<__hip_bfloat16>>(void* buf, size_t N,
-                                                                                       float scale) {
-    return split_storage_view<__hip_bfloat16>(buf, N, scale);
-}
 
-// The two passes of one step of every active job.  The grid is fixed
-// (persistent); workgroup b takes items b', b' + G, ... where b' spreads
-// contiguous item runs over the 8 XCDs so neighbouring tiles of a job share
-// an L2.
+template <typename S>
+struct BatchStorage;
+template <typename T>
+struct BatchStorage<LeanRaw<T>> {
+    using Src = RawPop<T>;
+    static __device__ __forceinline__ Src view(void* buf, size_t N, float) { return Src{(T*)buf, N}; }
+    static __device__ __forceinline__ LeanRaw<T> policy(void* in, void* out, size_t, float, f4*, int) {
+        return LeanRaw<T>{(const T*)in, (T*)out};
+    }
+};
+template <typename H>
+struct BatchStorage<LeanSplit<H>> {
+    using Src = SplitPop<H>;
+    static __device__ __forceinline__ Src view(void* buf, size_t N, float scale) {
+        return split_storage_view<H>(buf, N, scale);
+    }
+    static __device__ __forceinline__ LeanSplit<H> policy(void* in, void* out, size_t N, float scale, f4* ring,
+                                                          int TY) {
+        const SplitPop<H> a = split_storage_view<H>(in, N, scale), b = split_storage_view<H>(out, N, scale);
+        LeanSplit<H> st;
+        st.rin = a.rec;
+        st.din = a.dev;
+        st.rout = b.rec;
+        st.dout = b.dev;
+        st.codec = a;
+        st.ring = ring;
+        st.TY = TY;
+        return st;
+    }
+};
+
+// Workgroup b of a persistent launch takes items b', b' + G, ... where b'
+// spreads contiguous item runs over the 8 XCDs so neighbouring tiles of a job
+// share an L2.
 __device__ __forceinline__ int persistent_start() {
     const int G = gridDim.x;
     int b = blockIdx.x;
@@ -94,62 +112,74 @@ __device__ __forceinline__ int persistent_start() {
 }
 
 template <typename R>
-__device__ __forceinline__ void item_tile(const BatchJob<R>& J, const WorkItem& it, int& x0, int& y0, int& za,
-                                          int& zb) {
-    const int tile = it.block % J.tiles;
-    const int chunk = it.block / J.tiles;
-    x0 = (tile % J.fs.tiles_x) * kBatchTX;
-    y0 = (tile / J.fs.tiles_x) * J.fs.TY;
-    za = chunk * J.fs.TZ;
-    zb = min(za + J.fs.TZ, J.g.nz);
+__device__ __forceinline__ bool job_live(const BatchJob<R>& J, long long gs) {
+    return J.active && gs >= J.first && gs < J.last;
 }
 
-template <typename R, typename S>
-__global__ __launch_bounds__(kBatchThreads, Occupancy<S>::waves) void batch_phase_kernel(
-    const BatchJob<R>* __restrict__ jobs, const WorkItem* __restrict__ items, const int* __restrict__ n_items,
-    const long long* __restrict__ gstep) {
-    extern __shared__ unsigned char lds_raw[];
-    const int n = *n_items;
+// Assembly: phi of the face sites of every live job's current state.
+// n_items[0] tile items come first in the list, then n_items[1] assembly items.
+template <typename R, typename S, int TY>
+__global__ __launch_bounds__(kAsmThreads) void batch_assemble_kernel(const BatchJob<R>* __restrict__ jobs,
+                                                                     const WorkItem* __restrict__ items,
+                                                                     const int* __restrict__ n_items,
+                                                                     const long long* __restrict__ gstep) {
+    using B = BatchStorage<S>;
+    const int n0 = n_items[0], n = n_items[1];
     const long long gs = *gstep;
     for (int w = persistent_start(); w < n; w += gridDim.x) {
-        const WorkItem it = items[w];
+        const WorkItem it = items[n0 + w];
         const BatchJob<R>& J = jobs[it.slot];
-        if (!J.active || gs < J.first || gs >= J.last) continue;  // uniform over the workgroup
+        if (!job_live(J, gs)) continue;  // uniform over the workgroup
         const int par = (int)((gs - J.first) & 1);
-        const S src = storage_view<S>(J.buf[par], (size_t)J.g.N, J.scale);
-        int x0, y0, za, zb;
-        item_tile(J, it, x0, y0, za, zb);
-        RecRing<kBatchTX> rr{reinterpret_cast<f4*>(lds_raw), J.fs.TY + 2};
-        Geom g = J.g;
-        if (gs == J.first && J.fresh) g.moving = 0;  // the initial state was not collided
-        phase_tile<R, S, kBatchTX>(g, src, (R*)J.phi, rr, J.fs.TY, x0, y0, za, zb);
+        const typename B::Src src = B::view(J.buf[par], (size_t)J.g.N, J.scale);
+        assemble_site<R, typename B::Src, kTX, TY>(J.g, src, J.faces, (Part2<R>*)J.part[par],
+                                                  it.block * kAsmThreads + (int)threadIdx.x);
     }
 }
 
-template <typename R, typename S>
-__global__ __launch_bounds__(kBatchThreads, Occupancy<S>::waves) void batch_collide_kernel(
-    const BatchJob<R>* __restrict__ jobs, const WorkItem* __restrict__ items, const int* __restrict__ n_items,
-    const long long* __restrict__ gstep) {
+// LDS of the batch tile kernel: that of a lean tile with the batch halo.
+template <typename S, int TY>
+__host__ __device__ constexpr size_t batch_lds_bytes() {
+    return lean_lds_bytes<S, TY, kBatchH>();
+}
+
+// Tiles: collide, stream and gather the next state's phase sums of every
+// live job's tile items.
+template <typename S, int TY>
+__global__ __launch_bounds__(kTX * TY) void batch_tile_kernel(const BatchJob<typename S::R>* __restrict__ jobs,
+                                                              const WorkItem* __restrict__ items,
+                                                              const int* __restrict__ n_items,
+                                                              const long long* __restrict__ gstep) {
+    using R = typename S::R;
+    using B = BatchStorage<S>;
     extern __shared__ unsigned char lds_raw[];
-    const int n = *n_items;
+    R* ringb = reinterpret_cast<R*>(lds_raw);
+    size_t off = (phi_ring_bytes<R, kTX, kBatchH>(TY) + 15) & ~size_t(15);
+    f4* rec_ring = reinterpret_cast<f4*>(lds_raw + off);
+    off += S::ring_bytes(TY);
+    R* xch = reinterpret_cast<R*>(lds_raw + off);
+    Part2<R>* vs = reinterpret_cast<Part2<R>*>(lds_raw + off + lean_xch_bytes<R, TY>());
+    const int n = n_items[0];
     const long long gs = *gstep;
     for (int w = persistent_start(); w < n; w += gridDim.x) {
         const WorkItem it = items[w];
         const BatchJob<R>& J = jobs[it.slot];
-        if (!J.active || gs < J.first || gs >= J.last) continue;  // uniform over the workgroup
+        if (!job_live(J, gs)) continue;  // uniform over the workgroup
         const int par = (int)((gs - J.first) & 1);
-        const S src = storage_view<S>(J.buf[par], (size_t)J.g.N, J.scale);
-        const S dst = storage_view<S>(J.buf[par ^ 1], (size_t)J.g.N, J.scale);
-        int x0, y0, za, zb;
-        item_tile(J, it, x0, y0, za, zb);
-        PhiRing<R, kBatchTX, kBatchH> ring{reinterpret_cast<R*>(lds_raw), J.fs.TY + 2 * kBatchH};
-        RecRing<kBatchTX> rr{reinterpret_cast<f4*>(lds_raw + ((phi_ring_bytes<R, kBatchTX, kBatchH>(J.fs.TY) + 15) &
-                                                               ~size_t(15))),
-                             J.fs.TY + 2};
-        Geom g = J.g;
-        if (gs == J.first && J.fresh) g.moving = 0;  // the initial state was not collided
-        fused_tile<R, S, S, kBatchTX, kBatchH>(g, src, dst, J.c, ring, J.fs.TY, x0, y0, za, zb,
-                                               (const R*)J.phi, rr);
+        const Geom g = J.g;
+        const S st = B::policy(J.buf[par], J.buf[par ^ 1], (size_t)g.N, J.scale, rec_ring, TY);
+        const int tile = it.block % J.tiles, chunk = it.block / J.tiles;
+        const int x0 = (tile % J.fs.tiles_x) * kTX, y0 = (tile / J.fs.tiles_x) * TY;
+        const int za = chunk * J.fs.TZ, zb = min(za + J.fs.TZ, g.nz);
+        Part2<R>* const pin = (Part2<R>*)J.part[par];
+        Part2<R>* const pout = (Part2<R>*)J.part[par ^ 1];
+        if (g.wx || g.wy || g.wz)
+            lean_tile<S, TY, kBatchH, true>(g, st, J.c, ringb, xch, vs, x0, y0, za, zb, phi_of<kTX>(pin, g), pout,
+                                            phi_of<kTX>(pout, g));
+        else
+            lean_tile<S, TY, kBatchH, false>(g, st, J.c, ringb, xch, vs, x0, y0, za, zb, phi_of<kTX>(pin, g), pout,
+                                             phi_of<kTX>(pout, g));
+        __syncthreads();  // the next item restages every LDS ring
     }
 }
 
@@ -157,17 +187,17 @@ __global__ void batch_tick_kernel(long long* gstep) {
     if (blockIdx.x == 0 && threadIdx.x == 0) gstep[0] = gstep[0] + 1;
 }
 
-// Default tile rows of the batched passes (measured on MI355X).
-int batch_rows(int storage) { return storage == LB_STORE_F64 ? 8 : 4; }
+// Tile rows of the batched step: 8 (4 on request); the lean tile is
+// instantiated for these two.
+int batch_rows(int want) { return want > 0 && want < 8 ? 4 : 8; }
 
-size_t batch_phase_lds(int storage, int TY) {
-    return storage >= LB_STORE_F16 ? rec_ring_bytes<kBatchTX>(TY) : 0;
-}
-
-size_t batch_collide_lds(int storage, int TY) {
-    const size_t phi = storage == LB_STORE_F64 ? phi_ring_bytes<double, kBatchTX, kBatchH>(TY)
-                                               : phi_ring_bytes<float, kBatchTX, kBatchH>(TY);
-    return ((phi + 15) & ~size_t(15)) + batch_phase_lds(storage, TY);
+size_t batch_tile_lds(int storage, int TY) {
+    switch (storage) {
+        case LB_STORE_F64: return TY == 4 ? batch_lds_bytes<LeanRaw<double>, 4>() : batch_lds_bytes<LeanRaw<double>, 8>();
+        case LB_STORE_F32: return TY == 4 ? batch_lds_bytes<LeanRaw<float>, 4>() : batch_lds_bytes<LeanRaw<float>, 8>();
+        default:
+            return TY == 4 ? batch_lds_bytes<LeanSplit<__half>, 4>() : batch_lds_bytes<LeanSplit<__half>, 8>();
+    }
 }
 
 }  // namespace lbm
@@ -236,7 +266,6 @@ struct HostJob {
     lb_params p;
     size_t off = 0, bytes = 0;
     long long first = 0, last = 0;
-    bool fresh = false;
     Coeffs<double> cd;
     Coeffs<float> cf;
     FusedShape fs;
@@ -253,8 +282,8 @@ struct lb_batch_t {
     Arena arena;
     std::vector<HostJob> jobs;
     void* d_jobs = nullptr;     // BatchJob<R>[max_jobs]
-    WorkItem* d_items = nullptr;
-    int* d_nitems = nullptr;
+    WorkItem* d_items = nullptr;  // tile items, then assembly items
+    int* d_nitems = nullptr;      // [2]: tile items, assembly items
     long long* d_gstep = nullptr;
     int items_cap = 0;
     long long gstep = 0;        // host mirror of the device counter
@@ -262,20 +291,24 @@ struct lb_batch_t {
     size_t staging_bytes = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    int grid = 0;
-    int ty = 4, tz = 32;        // tile rows and chunk planes of every job (fixed at creation)
+    int grid = 0;               // workgroups of the persistent tile launch (all resident)
+    int agrid = 0;              // workgroups of the persistent assembly launch
+    int ty = 8, tz = 32;        // tile rows and chunk planes of every job (fixed at creation)
     bool own_stream = false;
 };
 
 namespace {
 
-// Two population buffers and the phase field.
-size_t job_bytes(int storage, size_t N) {
-    const size_t half = (lbm::pop_bytes(storage, N) + 255) & ~size_t(255);
-    return 2 * half + N * (storage == LB_STORE_F64 ? 8 : 4);
+// Two population buffers and two phase-sum buffers.
+size_t job_half(int storage, size_t N) { return (lbm::pop_bytes(storage, N) + 255) & ~size_t(255); }
+
+size_t job_part(const lb_params& p) {
+    return (part_reals<kTX>(p.nx, p.ny, p.nz) * (p.storage == LB_STORE_F64 ? 8 : 4) + 255) & ~size_t(255);
 }
 
-size_t job_half(int storage, size_t N) { return (lbm::pop_bytes(storage, N) + 255) & ~size_t(255); }
+size_t job_bytes(const lb_params& p) {
+    return 2 * job_half(p.storage, (size_t)p.nx * p.ny * p.nz) + 2 * job_part(p);
+}
 
 float batch_scale(const lb_batch_t* b, const lb_params& p) {
     return b->storage == LB_STORE_F16 ? std::ldexp(1.0f, p.scale_log2 ? p.scale_log2 : 16) : 1.0f;
@@ -284,7 +317,7 @@ float batch_scale(const lb_batch_t* b, const lb_params& p) {
 FusedShape job_shape(const lb_batch_t* b, const lb_params& p) {
     FusedShape fs;
     fs.TY = b->ty;
-    fs.tiles_x = (p.nx + kBatchTX - 1) / kBatchTX;
+    fs.tiles_x = (p.nx + kTX - 1) / kTX;
     fs.tiles_y = (p.ny + fs.TY - 1) / fs.TY;
     fs.TZ = std::min(p.nz, b->tz);
     fs.chunks = (p.nz + fs.TZ - 1) / fs.TZ;
@@ -301,15 +334,17 @@ void fill_desc(const lb_batch_t* b, const HostJob& h, BatchJob<R>& d) {
     else
         d.c = h.cf;
     d.fs = h.fs;
-    const size_t half = job_half(b->storage, (size_t)h.p.nx * h.p.ny * h.p.nz);
-    d.buf[0] = b->arena_base + h.off;
-    d.buf[1] = b->arena_base + h.off + half;
-    d.phi = b->arena_base + h.off + 2 * half;
+    d.faces = face_set(d.g, kTX, h.fs.TY, h.fs.TZ);
+    const size_t half = job_half(b->storage, (size_t)h.p.nx * h.p.ny * h.p.nz), part = job_part(h.p);
+    char* base = b->arena_base + h.off;
+    d.buf[0] = base;
+    d.buf[1] = base + half;
+    d.part[0] = base + 2 * half;
+    d.part[1] = base + 2 * half + part;
     d.first = h.first;
     d.last = h.last;
     d.active = h.used ? 1 : 0;
     d.tiles = h.fs.tiles_x * h.fs.tiles_y;
-    d.fresh = h.fresh ? 1 : 0;
     d.scale = batch_scale(b, h.p);
 }
 
@@ -334,6 +369,15 @@ int upload_items(lb_batch_t* b) {
         if (!h.used) continue;
         for (int k = 0; k < h.fs.nblocks; ++k) items.push_back(WorkItem{s, k});
     }
+    int counts[2] = {(int)items.size(), 0};
+    for (int s = 0; s < b->max_jobs; ++s) {
+        const HostJob& h = b->jobs[s];
+        if (!h.used) continue;
+        const FaceSet f = face_set(make_geom(h.p), kTX, h.fs.TY, h.fs.TZ);
+        const int runs = (f.row_sites + f.edge_sites + kAsmThreads - 1) / kAsmThreads;
+        for (int k = 0; k < runs; ++k) items.push_back(WorkItem{s, k});
+    }
+    counts[1] = (int)items.size() - counts[0];
     if ((int)items.size() > b->items_cap) {
         // grow the work list; the graph holds its pointer, so drop the graph
         if (b->exec) (void)hipGraphExecDestroy(b->exec);
@@ -352,35 +396,59 @@ int upload_items(lb_batch_t* b) {
     int n = (int)items.size();
     int rc = LB_OK;
     if (n) rc = bcheck(hipMemcpyAsync(b->d_items, items.data(), sizeof(WorkItem) * n, hipMemcpyHostToDevice, b->stream), "upload work list");
-    if (!rc) rc = bcheck(hipMemcpyAsync(b->d_nitems, &n, sizeof(int), hipMemcpyHostToDevice, b->stream), "upload count");
+    if (!rc) rc = bcheck(hipMemcpyAsync(b->d_nitems, counts, sizeof(counts), hipMemcpyHostToDevice, b->stream), "upload counts");
     if (!rc) rc = bcheck(hipStreamSynchronize(b->stream), "sync");
     return rc;
 }
 
-template <typename R, typename S>
-int launch_batch_step(lb_batch_t* b) {
-    hipLaunchKernelGGL((batch_phase_kernel<R, S>), dim3(b->grid), dim3(kBatchThreads), batch_phase_lds(b->storage, b->ty),
-                       b->stream, (const BatchJob<R>*)b->d_jobs, b->d_items, b->d_nitems, b->d_gstep);
+template <typename S, int TY>
+const void* tile_kernel_of() {
+    return reinterpret_cast<const void*>(batch_tile_kernel<S, TY>);
+}
+
+template <typename S, int TY>
+int launch_batch_ty(lb_batch_t* b) {
+    using R = typename S::R;
+    hipLaunchKernelGGL((batch_assemble_kernel<R, S, TY>), dim3(b->agrid), dim3(kAsmThreads), 0, b->stream,
+                       (const BatchJob<R>*)b->d_jobs, b->d_items, b->d_nitems, b->d_gstep);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return bfail(LB_EDEVICE, std::string("batch_phase_kernel: ") + hipGetErrorString(e));
-    hipLaunchKernelGGL((batch_collide_kernel<R, S>), dim3(b->grid), dim3(kBatchThreads), batch_collide_lds(b->storage, b->ty),
-                       b->stream, (const BatchJob<R>*)b->d_jobs, b->d_items, b->d_nitems, b->d_gstep);
+    if (e != hipSuccess) return bfail(LB_EDEVICE, std::string("batch_assemble_kernel: ") + hipGetErrorString(e));
+    const size_t lds = batch_lds_bytes<S, TY>();
+    hipLaunchKernelGGL((batch_tile_kernel<S, TY>), dim3(b->grid), dim3(kTX * TY), lds, b->stream,
+                       (const BatchJob<R>*)b->d_jobs, b->d_items, b->d_nitems, b->d_gstep);
     e = hipGetLastError();
-    if (e != hipSuccess) return bfail(LB_EDEVICE, std::string("batch_collide_kernel: ") + hipGetErrorString(e));
+    if (e != hipSuccess) return bfail(LB_EDEVICE, std::string("batch_tile_kernel: ") + hipGetErrorString(e));
     hipLaunchKernelGGL(batch_tick_kernel, dim3(1), dim3(64), 0, b->stream, b->d_gstep);
     e = hipGetLastError();
     if (e != hipSuccess) return bfail(LB_EDEVICE, std::string("batch_tick_kernel: ") + hipGetErrorString(e));
     return LB_OK;
 }
 
+template <typename S>
+int launch_batch_step(lb_batch_t* b) {
+    return b->ty == 4 ? launch_batch_ty<S, 4>(b) : launch_batch_ty<S, 8>(b);
+}
+
 int batch_step_once(lb_batch_t* b) {
     switch (b->storage) {
-        case LB_STORE_F64: return launch_batch_step<double, RawPop<double>>(b);
-        case LB_STORE_F32: return launch_batch_step<float, RawPop<float>>(b);
-        case LB_STORE_F16: return launch_batch_step<float, SplitPop<__half>>(b);
-        case LB_STORE_BF16: return launch_batch_step<float, SplitPop<__hip_bfloat16>>(b);
+        case LB_STORE_F64: return launch_batch_step<LeanRaw<double>>(b);
+        case LB_STORE_F32: return launch_batch_step<LeanRaw<float>>(b);
+        case LB_STORE_F16: return launch_batch_step<LeanSplit<__half>>(b);
+        case LB_STORE_BF16: return launch_batch_step<LeanSplit<__hip_bfloat16>>(b);
     }
     return bfail(LB_EINVAL, "unknown storage");
+}
+
+// The tile kernel of the batch (for its LDS opt-in and occupancy).
+const void* batch_tile_kernel_of(int storage, int TY) {
+    switch (storage) {
+        case LB_STORE_F64: return TY == 4 ? tile_kernel_of<LeanRaw<double>, 4>() : tile_kernel_of<LeanRaw<double>, 8>();
+        case LB_STORE_F32: return TY == 4 ? tile_kernel_of<LeanRaw<float>, 4>() : tile_kernel_of<LeanRaw<float>, 8>();
+        case LB_STORE_F16: return TY == 4 ? tile_kernel_of<LeanSplit<__half>, 4>() : tile_kernel_of<LeanSplit<__half>, 8>();
+        default:
+            return TY == 4 ? tile_kernel_of<LeanSplit<__hip_bfloat16>, 4>()
+                           : tile_kernel_of<LeanSplit<__hip_bfloat16>, 8>();
+    }
 }
 
 int ensure_graph(lb_batch_t* b) {
@@ -428,6 +496,8 @@ LatticeView job_view(lb_batch_t* b, int slot, void* cur, void* nxt, void* pendin
     v.phi = nullptr;
     v.cd = h.cd;
     v.cf = h.cf;
+    v.shape_set = true;
+    v.shape = h.fs;
     return v;
 }
 
@@ -442,12 +512,7 @@ void* job_current(lb_batch_t* b, int slot) {
     return b->arena_base + h.off + ((done & 1) ? half : 0);
 }
 
-LatticeView current_view(lb_batch_t* b, int slot) {
-    HostJob& h = b->jobs[slot];
-    LatticeView v = job_view(b, slot, job_current(b, slot), nullptr, nullptr);
-    if (h.fresh && std::min(b->gstep, h.last) == h.first) v.g.moving = 0;  // not collided yet
-    return v;
-}
+LatticeView current_view(lb_batch_t* b, int slot) { return job_view(b, slot, job_current(b, slot), nullptr, nullptr); }
 
 }  // namespace
 
@@ -481,20 +546,32 @@ int lb_batch_create(int32_t max_jobs, int64_t arena_bytes, int32_t storage, int3
     int dev = 0, cus = 0;
     (void)hipGetDevice(&dev);
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
-    b->grid = cus * 4;
-    // tile shape: the process setting (lb_set_tiles) or the default; rows halved
-    // until both passes fit the 64 KB of LDS a kernel gets without opting in
+    // tile shape: the process setting (lb_set_tiles) or the default
     const TileSetting ts = tile_setting(TILE_BATCH, storage);
-    b->ty = ts.ty > 0 ? ts.ty : batch_rows(storage);
-    while (b->ty > 1 && batch_collide_lds(storage, b->ty) > 65536) b->ty /= 2;
+    b->ty = batch_rows(ts.ty);
     b->tz = ts.tz > 0 ? ts.tz : 32;
+    // the tile launch holds as many workgroups as are resident at once (LDS
+    // beyond 64 KB needs the opt-in); the assembly launch 8 per CU
+    const void* kern = batch_tile_kernel_of(storage, b->ty);
+    const size_t lds = batch_tile_lds(storage, b->ty);
+    int per_cu = 0;
+    hipError_t he = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (he == hipSuccess)
+        he = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kTX * b->ty, lds);
+    if (he != hipSuccess || per_cu < 1) {
+        if (b->own_stream) (void)hipStreamDestroy(b->stream);
+        delete b;
+        return bfail(LB_EDEVICE, std::string("batch tile kernel does not fit a CU: ") + hipGetErrorString(he));
+    }
+    b->grid = cus * per_cu;
+    b->agrid = cus * 8;
     int rc = LB_OK;
     if ((rc = bcheck(hipMalloc((void**)&b->arena_base, (size_t)arena_bytes), "hipMalloc arena")) ||
         (rc = bcheck(hipMalloc(&b->d_jobs, desc_size(storage) * max_jobs), "hipMalloc job table")) ||
-        (rc = bcheck(hipMalloc((void**)&b->d_nitems, sizeof(int)), "hipMalloc count")) ||
+        (rc = bcheck(hipMalloc((void**)&b->d_nitems, 2 * sizeof(int)), "hipMalloc counts")) ||
         (rc = bcheck(hipMalloc((void**)&b->d_gstep, sizeof(long long)), "hipMalloc step counter")) ||
         (rc = bcheck(hipMemsetAsync(b->d_jobs, 0, desc_size(storage) * max_jobs, b->stream), "clear job table")) ||
-        (rc = bcheck(hipMemsetAsync(b->d_nitems, 0, sizeof(int), b->stream), "clear count")) ||
+        (rc = bcheck(hipMemsetAsync(b->d_nitems, 0, 2 * sizeof(int), b->stream), "clear counts")) ||
         (rc = bcheck(hipMemsetAsync(b->d_gstep, 0, sizeof(long long), b->stream), "clear counter")) ||
         (rc = upload_items(b))) {
         lb_batch_destroy(b);
@@ -524,11 +601,13 @@ int lb_batch_destroy(lb_batch_t* b) {
 int64_t lb_batch_job_bytes(const lb_params* p) {
     std::string why;
     if (validate_params(p, why) != LB_OK) return -1;
-    return (int64_t)((job_bytes(p->storage, (size_t)p->nx * p->ny * p->nz) + 511) & ~size_t(511));
+    return (int64_t)((job_bytes(*p) + 511) & ~size_t(511));
 }
 
-// Admission: validate, place in the arena, write the initial state and (for
-// 16-bit storage) take the first step from the raw FP32 initial state.
+// Admission: validate, place in the arena, write the initial state and take
+// the job's first step (for 16-bit storage from the raw FP32 initial state)
+// with the one-read step of a single lattice on the batch's tile boxes: the
+// job then enters the batch with its state's phase sums.
 static int batch_admit(lb_batch_t* b, const lb_params* params, int64_t steps, int32_t* slot,
                        int (*init)(lb_batch_t*, const LatticeView&, const void*), const void* ctx) {
     if (!b || !params || !slot) return bfail(LB_EINVAL, "NULL argument");
@@ -540,6 +619,13 @@ static int batch_admit(lb_batch_t* b, const lb_params* params, int64_t steps, in
     if (make_geom(*params).moving) return bfail(LB_EINVAL, "batched jobs do not support moving walls");
     if (params->model != LB_MODEL_COLOUR_GRADIENT)
         return bfail(LB_EINVAL, "batched jobs use the colour-gradient model");
+    {
+        // 32-bit byte offsets of the tile kernel's buffer resources
+        const uint64_t n = (uint64_t)params->nx * params->ny * params->nz;
+        const uint64_t span = b->storage >= LB_STORE_F16 ? 2 * (uint64_t)Q * n > 32 * n ? 2 * (uint64_t)Q * n : 32 * n
+                                                         : (uint64_t)kResArrays * (b->storage == LB_STORE_F64 ? 8 : 4) * n;
+        if (span >= ((uint64_t)1 << 32)) return bfail(LB_EINVAL, "job too large for the batched step");
+    }
     if (steps < 0) return bfail(LB_EINVAL, "steps must be >= 0");
     // a 16-bit job's raw FP32 initial state lives in the shared staging area
     // only until its first step (taken here) encodes it into its own buffers
@@ -553,14 +639,14 @@ static int batch_admit(lb_batch_t* b, const lb_params* params, int64_t steps, in
         }
     if (s < 0) return bfail(LB_ENOMEM, "no free job slot");
     const size_t N = (size_t)params->nx * params->ny * params->nz;
-    const size_t bytes = (job_bytes(params->storage, N) + 511) & ~size_t(511);
+    const size_t bytes = (job_bytes(*params) + 511) & ~size_t(511);
     size_t off = 0;
     if (!b->arena.alloc(bytes, off)) return bfail(LB_ENOMEM, "arena has no room for this job");
     HostJob& h = b->jobs[s];
     h = HostJob();
     h.p = *params;
     if (h.p.scale_log2 == 0) h.p.scale_log2 = 16;
-    h.p.kernel = LB_KERNEL_TWOPASS;
+    h.p.kernel = LB_KERNEL_FUSED;
     h.off = off;
     h.bytes = bytes;
     h.cd = make_coeffs<double>(h.p);
@@ -568,27 +654,19 @@ static int batch_admit(lb_batch_t* b, const lb_params* params, int64_t steps, in
     h.fs = job_shape(b, h.p);
     char* b0 = b->arena_base + off;
     char* b1 = b0 + job_half(b->storage, N);
+    char* p0 = b0 + 2 * job_half(b->storage, N);
     const bool split = b->storage >= LB_STORE_F16;
-    int rc = LB_OK;
+    int rc = ensure_staging(b, (split ? lbm::pop_bytes(LB_STORE_F32, N) : 0) + 5 * N * sizeof(double) + 64);
     long long done = 0;
-    if (split) {
-        rc = ensure_staging(b, lbm::pop_bytes(LB_STORE_F32, N) + 5 * N * sizeof(double));
-        if (!rc) {
-            LatticeView v = job_view(b, s, b0, b1, b->staging);
-            v.g.moving = 0;  // the first step reads the initial, not collided, state
-            v.phi = b1 + job_half(b->storage, N);  // the job's phase field
-            rc = init(b, v, ctx);
-            if (!rc && steps > 0) {
-                // first step from the raw FP32 initial state into 16-bit storage
-                rc = launch_step(v, LB_KERNEL_TWOPASS, nullptr);
-                done = 1;
-            }
-        }
-    } else {
-        rc = ensure_staging(b, 5 * N * sizeof(double) + 64);
-        if (!rc) {
-            LatticeView v = job_view(b, s, b0, b1, nullptr);
-            rc = init(b, v, ctx);
+    if (!rc) {
+        LatticeView v = job_view(b, s, b0, b1, split ? b->staging : nullptr);
+        v.part_in = p0;
+        v.part_out = p0 + job_part(h.p);
+        v.part_valid = false;
+        rc = init(b, v, ctx);
+        if (!rc && steps > 0) {
+            rc = launch_step(v, LB_KERNEL_FUSED, nullptr);
+            done = 1;
         }
     }
     if (!rc) rc = bcheck(hipStreamSynchronize(b->stream), "sync");
@@ -598,7 +676,6 @@ static int batch_admit(lb_batch_t* b, const lb_params* params, int64_t steps, in
         return rc;
     }
     h.used = true;
-    h.fresh = (done == 0);
     h.first = b->gstep - done;
     h.last = h.first + steps;
     rc = upload_desc(b, s);

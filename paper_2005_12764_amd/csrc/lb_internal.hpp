@@ -25,6 +25,8 @@ struct LatticeView {
     void* part_in = nullptr;   // phase sums and phase field of the current state (one-read step)
     void* part_out = nullptr;  // the same, written by the one-read step for the next state
     bool part_valid = false;   // part_in holds the current state's sums
+    bool shape_set = false;    // the one-read step uses `shape` (not the lattice's own tile shape)
+    FusedShape shape{};
     Coeffs<double> cd;
     Coeffs<float> cf;
 };

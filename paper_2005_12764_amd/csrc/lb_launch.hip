@@ -177,7 +177,7 @@ int single_ty(const LatticeView& v, const Src& src, const Dst& dst, const Coeffs
 template <typename R, typename Src, typename Dst>
 int single_pass(const LatticeView& v, const Src& src, const Dst& dst, const Coeffs<R>& c, const StepEvents* t) {
     if (!v.part_in || !v.part_out) return set_error(LB_EINVAL, "one-read step without its phase buffers");
-    const FusedShape fs = tile_shape(*v.p, TILE_SINGLE);
+    const FusedShape fs = v.shape_set ? v.shape : tile_shape(*v.p, TILE_SINGLE);
     if (t) (void)hipEventRecord(t->ev[0], v.stream);
     int rc;
     if (fs.TY == kSingleTY) rc = single_ty<R, Src, Dst, kSingleTY>(v, src, dst, c, fs, t);

@@ -279,8 +279,8 @@ inline FaceSet face_set(const Geom& g, int TX, int TY, int TZ) {
 // phi of the face sites from their own partial sums, the foreign terms of
 // the z and y faces and the x-face sums.
 template <typename R, typename Src, int TX, int TY>
-__global__ __launch_bounds__(256) void assemble_kernel(Geom g, Src src, FaceSet fs, Part2<R>* __restrict__ part) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void assemble_site(const Geom& g, const Src& src, const FaceSet& fs,
+                                              Part2<R>* __restrict__ part, int k) {
     int x, y, z;
     if (k < fs.row_sites) {
         const int r = k / g.nx, zrows = fs.nzf * g.ny;
@@ -320,6 +320,12 @@ __global__ __launch_bounds__(256) void assemble_kernel(Geom g, Src src, FaceSet 
         rc += X.rc;
     }
     phi_of<TX>(part, g)[s] = dn / rc;
+}
+
+// Face site k of the enumeration above, one per thread.
+template <typename R, typename Src, int TX, int TY>
+__global__ __launch_bounds__(256) void assemble_kernel(Geom g, Src src, FaceSet fs, Part2<R>* __restrict__ part) {
+    assemble_site<R, Src, TX, TY>(g, src, fs, part, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // Exchange slot of a direction with c_y != 0 (the in-plane neighbours in

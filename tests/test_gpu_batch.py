@@ -1,7 +1,8 @@
 """GPU tests of the batched step, the droplet initialiser and the serving loop.
 
 - a job's result is bitwise the same alone in a batch, in a mix of uneven jobs,
-  and as a single lattice; and matches the oracle (FP32) within 1e-5;
+  and as a single lattice stepped by the one-read step on the same tile boxes
+  (8 rows, 32-plane chunks); and matches the oracle (FP32) within 1e-5;
 - jobs stop at their own step counts; graph replays equal eager steps;
 - the arena enforces the HBM budget and is reused after removal;
 - the droplet initialiser reproduces the host generator's fields;
@@ -18,6 +19,21 @@ from paper_2005_12764_amd import workloads as W
 from tests.helpers import oracle_params, state_errors
 
 pytestmark = pytest.mark.gpu
+
+# the batch's default tile boxes: 8-row tiles, 32-plane chunks
+BATCH_TY, BATCH_TZ = 8, 32
+
+
+def single_one_read(params, rr, rb, steps):
+    """The job as a single lattice, one-read step on the batch's tile boxes."""
+    st = params["storage"]
+    lb.lb_set_tiles(lb.TILES_ONE_READ, st, BATCH_TY, BATCH_TZ)
+    try:
+        with lb.Lattice(dict(params, kernel=lb.KERNEL_FUSED)) as L:
+            L.init(rr, rb).step(steps)
+            return L.state()
+    finally:
+        lb.lb_set_tiles(lb.TILES_ONE_READ, st, 0, 0)
 
 
 def _jobs(storage):
@@ -46,17 +62,22 @@ def test_job_alone_equals_job_in_mix_and_single_lattice(storage):
         mixed = B.state(sa)
         assert B.job_steps(sa) == steps and B.job_steps(sc) == steps and B.job_steps(sb) == steps + 7
     assert np.array_equal(alone, mixed)
-    # the batch runs the single lattice's two-pass tile code: bitwise equal;
-    # the single-pass kernel evaluates the same formulas in another order of
-    # contraction, so it agrees to rounding
-    for kernel in (lb.KERNEL_TWOPASS, lb.KERNEL_FUSED):
-        with lb.Lattice(dict(a.params, storage=storage, kernel=kernel)) as L:
-            L.init(a.rho_r, a.rho_b).step(steps)
-            single = L.state()
-        if kernel == lb.KERNEL_TWOPASS:
-            assert np.array_equal(alone, single)
-        else:
-            assert state_errors(single, alone)["worst"] < 1e-6
+    # the batch runs the single lattice's one-read tile code on the same tile
+    # boxes: bitwise equal; the two-pass step gathers phi in another order of
+    # summation, so it agrees to rounding
+    single = single_one_read(dict(a.params, storage=storage), a.rho_r, a.rho_b, steps)
+    assert np.array_equal(alone, single)
+    with lb.Lattice(dict(a.params, storage=storage, kernel=lb.KERNEL_TWOPASS)) as L:
+        L.init(a.rho_r, a.rho_b).step(steps)
+        two = L.state()
+    assert state_errors(two, alone)["worst"] < (1e-6 if storage == W.F32 else 1e-3)
+    for job in (b, c):
+        with lb.Batch(8, 1 << 30, storage, graph_steps=20) as B:
+            sl = B.add(job.params, job.rho_r, job.rho_b, steps=steps)
+            B.step(steps)
+            got = B.state(sl)
+        assert np.array_equal(got, single_one_read(dict(job.params, storage=storage), job.rho_r, job.rho_b,
+                                                   steps)), job.name
     if storage == W.F32:
         ref = O.step(oracle_params(a.params), O.init(oracle_params(a.params), a.rho_r, a.rho_b), steps)
         assert state_errors(mixed, ref)["worst"] < 1e-5
@@ -138,10 +159,7 @@ def test_f16_job_with_its_own_scale_matches_single_lattice():
             sl = B.add(p, b.rho_r, b.rho_b, steps=30)
             B.step(30)
             batched = B.state(sl)
-        with lb.Lattice(dict(p, kernel=lb.KERNEL_TWOPASS)) as L:
-            L.init(b.rho_r, b.rho_b).step(30)
-            single = L.state()
-        assert np.array_equal(batched, single), s2
+        assert np.array_equal(batched, single_one_read(p, b.rho_r, b.rho_b, 30)), s2
 
 
 def test_zero_step_16bit_job_is_rejected():
@@ -158,3 +176,28 @@ def test_zero_step_16bit_job_is_rejected():
         with lb.Lattice(p) as L:
             L.init(b.rho_r, b.rho_b)
             assert np.array_equal(f, L.state())
+
+
+@pytest.mark.parametrize("storage", [W.F64, W.BF16])
+def test_four_row_tiles_and_short_chunks_match_single_lattice(storage):
+    # the batch's other tile rows (4) with 16-plane chunks: ragged x tiles,
+    # walls and a chunk shorter than the rest, bitwise the single lattice's
+    # one-read step on the same boxes
+    _, _, c = _jobs(storage)
+    p = dict(c.params, storage=storage)
+    lb.lb_set_tiles(lb.TILES_BATCH, storage, 4, 16)
+    try:
+        with lb.Batch(2, 1 << 29, storage, graph_steps=10) as B:
+            sl = B.add(p, c.rho_r, c.rho_b, steps=25)
+            B.step(25)
+            got = B.state(sl)
+    finally:
+        lb.lb_set_tiles(lb.TILES_BATCH, storage, 0, 0)
+    lb.lb_set_tiles(lb.TILES_ONE_READ, storage, 4, 16)
+    try:
+        with lb.Lattice(dict(p, kernel=lb.KERNEL_FUSED)) as L:
+            L.init(c.rho_r, c.rho_b).step(25)
+            single = L.state()
+    finally:
+        lb.lb_set_tiles(lb.TILES_ONE_READ, storage, 0, 0)
+    assert np.array_equal(got, single)
