@@ -27,6 +27,9 @@
 namespace lbm {
 
 __device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+// Keep a wave-uniform value in a vector register.
+__device__ __forceinline__ void in_vgpr(float& v) { asm volatile("" : "+v"(v)); }
+__device__ __forceinline__ void in_vgpr(double& v) { asm volatile("" : "+v"(v)); }
 
 // The 2 Q population arrays of a buffer as four buffer resources of up to
 // ten arrays each: a pull or store is then one buffer access with the row in
@@ -60,6 +63,33 @@ __device__ __forceinline__ void res_store(float v, __amdgpu_buffer_rsrc_t r, uns
 __device__ __forceinline__ void res_store(double v, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
     using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, voff, soff, 2);
+}
+
+// Resource over n values of an array whose pointer is made opaque first (the
+// resource is then rebuilt where it is used instead of held in scalar
+// registers across the loop).
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t array_res(const T* p, unsigned n) {
+    asm volatile("" : "+s"(p));
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(p), 0, (int)(n * (unsigned)sizeof(T)), (int)kRsrcWord3);
+}
+// phase-sum pair (own sums of a face site), 8 or 16 bytes
+__device__ __forceinline__ void res_store(const Part2<float>& v, __amdgpu_buffer_rsrc_t r, unsigned voff,
+                                          unsigned soff) {
+    using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, voff, soff, 0);
+}
+__device__ __forceinline__ void res_store(const Part2<double>& v, __amdgpu_buffer_rsrc_t r, unsigned voff,
+                                          unsigned soff) {
+    using V = decltype(__builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(V, v), r, voff, soff, 0);
+}
+__device__ __forceinline__ void res_store_cached(float v, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+}
+__device__ __forceinline__ void res_store_cached(double v, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, voff, soff, 0);
 }
 
 // Value of lane l-1 of the wavefront (0 in lane 0) and of lane l+1 (0 in
@@ -119,11 +149,16 @@ struct LeanRaw {
     const T* fin;
     T* fout;
     __host__ __device__ static constexpr size_t ring_bytes(int) { return 0; }
-    __device__ __forceinline__ void stage(const Geom&, int, int, int, int, int, int) const {}
+    // nothing is loaded ahead: the pulls read their sources directly
+    struct Pre {};
+    __device__ __forceinline__ void stage_load(const Geom&, int, int, int, int, int, Pre&) const {}
+    __device__ __forceinline__ void stage_store(int, int, int, const Pre&) const {}
+    template <bool W>
+    __device__ __forceinline__ void dev_load(const Geom&, int, int, const LeanLane&, Pre&) const {}
 
     template <bool W>
-    __device__ __forceinline__ void pull(const Geom& g, const LeanPlane& P, const LeanLane& ln, R (&t)[Q],
-                                         R (&d)[Q]) const {
+    __device__ __forceinline__ void pull(const Geom& g, const LeanPlane& P, const LeanLane& ln, const Pre&,
+                                         R (&t)[Q], R (&d)[Q]) const {
         using L = Lattice;
         const T* fin_p = fin;
         asm volatile("" : "+s"(fin_p));  // resources rebuilt each plane (short-lived scalar registers)
@@ -223,62 +258,110 @@ struct LeanSplit {
         return __builtin_amdgcn_make_buffer_rsrc(const_cast<H*>(p), 0, (int)(Q * N * 2u), (int)kRsrcWord3);
     }
 
+    // Loaded one plane ahead, so that their latency overlaps a collision:
+    // records of two ring rows (and of the two columns past the tile) for the
+    // next staging, and the 16-bit deviations of the next site's pulls.
+    struct Pre {
+        f4 a0[2], a1[2], b0[2], b1[2];
+        unsigned dv[Q];  // the 16-bit deviations, one per register (two per register would make
+                         // every load wait at once for the packing)
+    };
+    static __device__ __forceinline__ H dev_of(unsigned v) { return __builtin_bit_cast(H, (unsigned short)v); }
+
     // Records of plane q, rows y0 - 1 .. y0 + TY and columns x0 - 1 .. x0 + 64
-    // (periodic wrap or mirror images beyond walls), into a ring slot.
-    __device__ __forceinline__ void stage(const Geom& g, int q, int slot, int x0, int y0, int ty, int lane) const {
+    // (periodic wrap or mirror images beyond walls): loaded into registers,
+    // then (stage_store) written to a ring slot.  Thread row ty takes ring
+    // rows ty and ty + TY (TY >= 2: at most two rows).
+    __device__ __forceinline__ void stage_load(const Geom& g, int q, int x0, int y0, int ty, int lane,
+                                               Pre& pr) const {
         const int zz = halo_coord(q, g.nz, g.wz);
         const unsigned ca = (unsigned)halo_coord(x0 - 1 + lane, g.nx, g.wx) * 32u;
         const unsigned cb = (unsigned)halo_coord(x0 - 1 + kTX + lane, g.nx, g.wx) * 32u;
         const __amdgpu_buffer_rsrc_t rr = rec_res(rin, (unsigned)g.N);
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int r = ty + k * TY;
+            if (r < TY + 2) {
+                const int yy = halo_coord(y0 - 1 + r, g.ny, g.wy);
+                const unsigned so = (unsigned)((zz * g.ny + yy) * g.nx) * 32u;
+                pr.a0[k] = res_load4(rr, ca, so);
+                pr.a1[k] = res_load4(rr, ca + 16u, so);
+                if (lane < 2) {
+                    pr.b0[k] = res_load4(rr, cb, so);
+                    pr.b1[k] = res_load4(rr, cb + 16u, so);
+                }
+            }
+        }
+    }
+    __device__ __forceinline__ void stage_store(int slot, int ty, int lane, const Pre& pr) const {
         f4* pl = plane(slot);
-        for (int r = ty; r < TY + 2; r += TY) {
-            const int yy = halo_coord(y0 - 1 + r, g.ny, g.wy);
-            const unsigned so = (unsigned)((zz * g.ny + yy) * g.nx) * 32u;
-            const f4 a0 = res_load4(rr, ca, so), a1 = res_load4(rr, ca + 16u, so);
-            pl[r * LXR + lane] = a0;
-            pl[half() + r * LXR + lane] = a1;
-            if (lane < 2) {
-                const f4 b0 = res_load4(rr, cb, so), b1 = res_load4(rr, cb + 16u, so);
-                pl[r * LXR + kTX + lane] = b0;
-                pl[half() + r * LXR + kTX + lane] = b1;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int r = ty + k * TY;
+            if (r < TY + 2) {
+                pl[r * LXR + lane] = pr.a0[k];
+                pl[half() + r * LXR + lane] = pr.a1[k];
+                if (lane < 2) {
+                    pl[r * LXR + kTX + lane] = pr.b0[k];
+                    pl[half() + r * LXR + kTX + lane] = pr.b1[k];
+                }
             }
         }
     }
 
+    // Deviations the pulls of site (x, yc, cz) read: direction i at the
+    // upstream site, or (a bounce-back off a y or z wall) the opposite
+    // direction at the site itself; the lanes next to an x wall re-read
+    // theirs in pull.
     template <bool W>
-    __device__ __forceinline__ void pull(const Geom& g, const LeanPlane& P, const LeanLane& ln, R (&t)[Q],
-                                         R (&d)[Q]) const {
+    __device__ __forceinline__ void dev_load(const Geom& g, int yc, int cz, const LeanLane& ln, Pre& pr) const {
         using L = Lattice;
-        const __amdgpu_buffer_rsrc_t dr = dev_res(din, P.Np);
+        unsigned Np = (unsigned)g.N;
+        asm volatile("" : "+s"(Np));
+        const unsigned own_row = (unsigned)((cz * g.ny + yc) * g.nx);
+        const __amdgpu_buffer_rsrc_t dr = dev_res(din, Np);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            bool bb;
+            const unsigned row = upstream_row<W>(g, yc, cz, L::cy[i], L::cz[i], bb);
+            const int a = (W && bb) ? L::opp[i] : i;
+            const unsigned col = (W && bb) ? ln.cx0 : (L::cx[i] > 0 ? ln.cxm : (L::cx[i] < 0 ? ln.cxp : ln.cx0));
+            const unsigned rw = (W && bb) ? own_row : row;
+            pr.dv[i] = __builtin_amdgcn_raw_buffer_load_b16(dr, col * 2u, ((unsigned)a * Np + rw) * 2u, 0);
+        }
+    }
+
+    template <bool W>
+    __device__ __forceinline__ void pull(const Geom& g, const LeanPlane& P, const LeanLane& ln, const Pre& pr,
+                                         R (&t)[Q], R (&d)[Q]) const {
+        using L = Lattice;
         const f4* pm = plane(P.rs[0]);
         const f4* p0 = plane(P.rs[1]);
         const f4* pp = plane(P.rs[2]);
         const int own = (ln.ty + 1) * LXR + ln.lane + 1;
-        auto dv = [&](int a, unsigned col, unsigned row) {
-            return __builtin_bit_cast(H, __builtin_amdgcn_raw_buffer_load_b16(dr, col * 2u, ((unsigned)a * P.Np + row) * 2u, 0));
-        };
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             bool bb;
-            const unsigned row = upstream_row<W>(g, P.yc, P.cz, L::cy[i], L::cz[i], bb);
+            (void)upstream_row<W>(g, P.yc, P.cz, L::cy[i], L::cz[i], bb);
             if (W && bb) {
-                const int o = L::opp[i];
-                codec.decode(i, o, p0[own], p0[half() + own], dv(o, ln.cx0, P.own_row), t[i], d[i]);
+                codec.decode(i, L::opp[i], p0[own], p0[half() + own], dev_of(pr.dv[i]), t[i], d[i]);
             } else {
                 // the source (x - c_i) in plane cz - c_z: cz - 1 is pm, cz + 1 is pp
                 const f4* pl = L::cz[i] > 0 ? pm : (L::cz[i] < 0 ? pp : p0);
                 const int pos = own - L::cy[i] * LXR - L::cx[i];
-                const unsigned col = L::cx[i] > 0 ? ln.cxm : (L::cx[i] < 0 ? ln.cxp : ln.cx0);
-                codec.decode(i, i, pl[pos], pl[half() + pos], dv(i, col, row), t[i], d[i]);
+                codec.decode(i, i, pl[pos], pl[half() + pos], dev_of(pr.dv[i]), t[i], d[i]);
             }
         }
         if constexpr (W) {
             if (ln.wall_xlo || ln.wall_xhi) {
+                const __amdgpu_buffer_rsrc_t dr = dev_res(din, P.Np);
 #pragma unroll
                 for (int i = 1; i < Q; ++i) {
                     if (!((L::cx[i] > 0 && ln.wall_xlo) || (L::cx[i] < 0 && ln.wall_xhi))) continue;
                     const int o = L::opp[i];
-                    codec.decode(i, o, p0[own], p0[half() + own], dv(o, ln.cx0, P.own_row), t[i], d[i]);
+                    const H dv = __builtin_bit_cast(H, __builtin_amdgcn_raw_buffer_load_b16(
+                                                           dr, ln.cx0 * 2u, ((unsigned)o * P.Np + P.own_row) * 2u, 0));
+                    codec.decode(i, o, p0[own], p0[half() + own], dv, t[i], d[i]);
                 }
             }
         }
@@ -358,7 +441,7 @@ __device__ __forceinline__ void lean_xedge_rows(const Geom& g, const R* __restri
 // all-periodic lattice carries none of their tests; the lanes next to an x
 // wall take their bounce-backs from a second, masked pull).
 template <typename S, int TY, int H, bool W>
-__device__ __forceinline__ void lean_tile(const Geom& g, const S& st, const Coeffs<typename S::R>& c,
+__device__ __forceinline__ void lean_tile(const Geom& g, const S& st, const Coeffs<typename S::R>& cs,
                                           typename S::R* __restrict__ ringb, typename S::R* __restrict__ xch,
                                           Part2<typename S::R>* __restrict__ vs, int x0, int y0, int za, int zb,
                                           const typename S::R* __restrict__ phi_in,
@@ -373,6 +456,25 @@ __device__ __forceinline__ void lean_tile(const Geom& g, const S& st, const Coef
     constexpr int PLANE = LY * LX;
     constexpr int XROW = 2 * kXchDirs * kLeanRowPad;  // exchange reals per tile row
     const unsigned N = (unsigned)g.N;  // byte offsets within a resource < 2^32 (checked on the host)
+    // the collision's real coefficients in vector registers: the loop holds
+    // more wave-uniform values than the scalar register file, and a VALU
+    // operation reads a vector register at no cost (the flags that steer
+    // control flow stay scalar)
+    Coeffs<R> c = cs;
+    in_vgpr(c.inv_nu_r);
+    in_vgpr(c.inv_nu_b);
+    in_vgpr(c.omega);
+    in_vgpr(c.half_A);
+    in_vgpr(c.beta);
+    in_vgpr(c.eps_g);
+    in_vgpr(c.eps_g2);
+    in_vgpr(c.g_iface);
+    in_vgpr(c.g_iface2);
+    in_vgpr(c.nc_strength);
+    in_vgpr(c.nc_hmin);
+    in_vgpr(c.fx);
+    in_vgpr(c.fy);
+    in_vgpr(c.fz);
     const int lane = threadIdx.x & 63;
     const int ty = wave_uniform(threadIdx.x >> 6);
     const int x = x0 + lane;
@@ -417,18 +519,26 @@ __device__ __forceinline__ void lean_tile(const Geom& g, const S& st, const Coef
     R pfa[NR], pfb[NR];
     auto fetch = [&](int q) {
         const int zz = halo_coord(q, g.nz, g.wz);
+        const __amdgpu_buffer_rsrc_t pr = array_res(phi_in, N);
 #pragma unroll
         for (int k = 0; k < NR; ++k) {
             const int r = ty + k * TY;
             if (r < LY) {
                 const int yy = halo_coord(y0 - H + r, g.ny, g.wy);
-                const R* rowp = phi_in + (size_t)(zz * g.ny + yy) * g.nx;
-                pfa[k] = rowp[ra];
-                pfb[k] = lane < 2 * H ? rowp[rb] : R(0);
+                const unsigned so = (unsigned)((zz * g.ny + yy) * g.nx) * (unsigned)sizeof(R);
+                pfa[k] = res_load(R(0), pr, (unsigned)ra * (unsigned)sizeof(R), so);
+                pfb[k] = lane < 2 * H ? res_load(R(0), pr, (unsigned)rb * (unsigned)sizeof(R), so) : R(0);
             }
         }
     };
     fetch(za - H);
+    // Values loaded one plane ahead (records to stage, deviations to pull)
+    // are loaded in every iteration, at the same point, for a plane clamped
+    // into the lattice: a value the loop carries then has a single source,
+    // and no register copy at the loop head has to wait for its load.  The
+    // loads of planes nothing uses are in bounds and few.
+    typename S::Pre pre;
+    st.stage_load(g, za - 2 * H + 1, x0, y0, ty, lane, pre);
 
     for (int p = za - H; p < zb + H; ++p) {
         const int slot = (p - (za - H)) % NP;
@@ -447,12 +557,18 @@ __device__ __forceinline__ void lean_tile(const Geom& g, const S& st, const Coef
         if constexpr (S::split) {
             // records of plane p - H + 1, the cz + 1 of the plane collided below
             const int qr = p - H + 1;
-            if (qr >= za - 1 && qr <= zb) st.stage(g, qr, (qr - (za - 1)) % 3, x0, y0, ty, lane);
+            if (qr >= za - 1 && qr <= zb) st.stage_store((qr - (za - 1)) % 3, ty, lane, pre);
         }
         __syncthreads();
-        if (p + 1 < zb + H) fetch(p + 1);
+        fetch(p + 1);
+        st.stage_load(g, p - H + 2, x0, y0, ty, lane, pre);
         const int cz = p - H;
-        if (cz < za) continue;  // uniform over the workgroup
+        if (cz < za) {
+            // deviations of plane cz + 1 (the first collided plane's in the
+            // last such iteration)
+            st.template dev_load<W>(g, yc, max(cz + 1, 0), ln, pre);
+            continue;  // uniform over the workgroup
+        }
         const int s0 = (cz - (za - H)) % NP;
         const int sm = (s0 + NP - 1) % NP, sp = (s0 + 1) % NP;
         // N re-read each plane: the array offsets a N then stay scalar
@@ -470,7 +586,8 @@ __device__ __forceinline__ void lean_tile(const Geom& g, const S& st, const Coef
         P.rs[2] = (cz + 1 - (za - 1)) % 3;
         // ---- pull (x, y, cz)
         R t[Q], d[Q];
-        st.template pull<W>(g, P, ln, t, d);
+        st.template pull<W>(g, P, ln, pre, t, d);
+        st.template dev_load<W>(g, yc, min(cz + 1, g.nz - 1), ln, pre);
         // ---- colour gradient from the ring: base at (ty + H - 1, lane + H - 1)
         R gx, gy, gz;
         {
@@ -588,9 +705,13 @@ __device__ __forceinline__ void lean_tile(const Geom& g, const S& st, const Coef
                 prev_dn += vd;
             }
             if (site_in) {
-                const size_t sm1 = (size_t)((cz - 1) * g.ny + y) * g.nx + x;
-                if (cz - 1 == za || face_xy) part_out[sm1] = Part2<R>{prev_dn, prev_rc};
-                else phi_out[sm1] = prev_dn / prev_rc;
+                const unsigned row = (unsigned)(((cz - 1) * g.ny + y) * g.nx);
+                if (cz - 1 == za || face_xy)
+                    res_store(Part2<R>{prev_dn, prev_rc}, array_res(part_out, N), (unsigned)x * sizeof(Part2<R>),
+                              row * (unsigned)sizeof(Part2<R>));
+                else
+                    res_store_cached(prev_dn / prev_rc, array_res(phi_out, N), (unsigned)x * sizeof(R),
+                                     row * (unsigned)sizeof(R));
             }
         }
         // destination cz: in-plane sources
@@ -619,7 +740,9 @@ __device__ __forceinline__ void lean_tile(const Geom& g, const S& st, const Coef
         cur_dn = next_dn;
         cur_rc = next_rc;
         // the chunk's last plane has no own sources above it
-        if (cz == zb - 1 && site_in) part_out[(size_t)(cz * g.ny + y) * g.nx + x] = Part2<R>{prev_dn, prev_rc};
+        if (cz == zb - 1 && site_in)
+            res_store(Part2<R>{prev_dn, prev_rc}, array_res(part_out, N), (unsigned)x * sizeof(Part2<R>),
+                      (unsigned)((cz * g.ny + y) * g.nx) * (unsigned)sizeof(Part2<R>));
         // no barrier here: the next staging overwrites ring slots that only
         // this plane's collide read, and every thread passed the barrier after
         // that collide before it gathers; the exchange rows are next written

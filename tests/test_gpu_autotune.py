@@ -1,6 +1,7 @@
 """Tile shapes on the GPU: results independent of the shape where the method
-fixes them, the one-read step safe across a change of shape, the tuner's
-choices runnable."""
+fixes them (two-pass steps), following the tile boxes where the phase sums
+do (one-read and batched steps), the one-read step safe across a change of
+shape, the tuner's choices runnable."""
 import numpy as np
 import pytest
 
@@ -69,7 +70,10 @@ def test_one_read_with_sixteen_rows(tiles):
     assert state_errors(straight, ref)["worst"] < 2e-6
 
 
-def test_batch_results_do_not_depend_on_tiles(tiles):
+def test_batch_results_follow_their_tile_boxes(tiles):
+    # the batched step is the one-read step on the batch's tile boxes: other
+    # boxes move the results by rounding only, and each shape equals the
+    # single lattice's one-read step on the same boxes bitwise
     jobs = [W.periodic_emulsion(seed=k, n=s) for k, s in enumerate((32, 48))]
 
     def run():
@@ -78,10 +82,17 @@ def test_batch_results_do_not_depend_on_tiles(tiles):
             B.step(20)
             return [B.state(s) for s in slots]
 
+    def single(w, ty, tz):
+        tiles(lb.TILES_ONE_READ, W.F16, ty, tz)
+        return _run(w, W.F16, lb.KERNEL_FUSED, 20)
+
     a = run()
-    tiles(lb.TILES_BATCH, W.F16, 2, 8)
+    tiles(lb.TILES_BATCH, W.F16, 4, 16)
     b = run()
-    assert all(np.array_equal(x, y) for x, y in zip(a, b))
+    for w, x, y in zip(jobs, a, b):
+        assert state_errors(x, y)["worst"] < 1e-3
+        assert np.array_equal(x, single(w, 8, 32))
+        assert np.array_equal(y, single(w, 4, 16))
 
 
 def test_tuner_picks_runnable_shapes(tmp_path, tiles):
