@@ -290,11 +290,15 @@ def main():
     ap.add_argument("--n", type=int, default=256, help="lattice side of the emulsion")
     ap.add_argument("--variants", default="f32,f16,bf16")
     ap.add_argument("--kernel", type=int, default=0, help="0 auto, 1 two-pass, 2 fused")
-    ap.add_argument("--cpu-steps", type=int, default=16,
-                    help="oracle steps of the full lattice on all host threads (about 30 s on 16)")
+    ap.add_argument("--cpu-steps", type=int, default=20,
+                    help="oracle steps of the full lattice on all host threads (about 35 s on 16)")
     ap.add_argument("--cpu-steps-1t", type=int, default=1, help="oracle steps on one thread (0 = skip)")
     ap.add_argument("--serve-jobs", type=int, default=200, help="jobs of the serving leg (0 = skip)")
-    ap.add_argument("--serve-rate", type=float, default=40.0)
+    ap.add_argument("--serve-rate", type=float, default=40.0,
+                    help="arrival rate of the serving leg (the design-sweep stream's 40 jobs/s)")
+    ap.add_argument("--serve-sat-rate", type=float, default=1000.0,
+                    help="arrival rate of a second serving leg that keeps the batch full "
+                         "(its aggregate rate measures the serving form's capacity; 0 = skip)")
     ap.add_argument("--serve-steps", type=int, default=500)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-korteweg", action="store_true", help="skip the Korteweg-diagnostic leg")
@@ -320,11 +324,13 @@ def main():
 
     # the serving leg's requests (droplet lists) are built by worker
     # processes before this process touches the GPU
-    reqs, prep = None, 0.0
+    reqs, prep, sat_reqs = None, 0.0, None
     if args.serve_jobs > 0:
         from paper_2005_12764_amd import serve as S
         t0 = time.perf_counter()
         reqs = S.make_requests(args.serve_jobs, seed=0, rate=args.serve_rate, steps=args.serve_steps)
+        if args.serve_sat_rate > 0:
+            sat_reqs = S.make_requests(args.serve_jobs, seed=0, rate=args.serve_sat_rate, steps=args.serve_steps)
         prep = time.perf_counter() - t0
         log("serving: %d requests prepared in %.1fs" % (len(reqs), prep))
 
@@ -343,6 +349,8 @@ def main():
         r = gpu_variant(w, st, args.steps, args.warmup, stream, args.kernel)
         r["mlups"] = w.sites / (r["ms_per_step"] * 1e-3) / 1e6
         r["algo_gbs"] = r["mlups"] * 1e6 * ALGO_BYTES[st] / 1e9
+        # the tile kernel alone (pass_ms[1]) against its algorithmic bytes
+        r["tile_algo_gbs"] = ALGO_BYTES[st] * w.sites / (r["pass_ms"][1] * 1e-3) / 1e9
         results[name] = r
         log("%s: %.3f ms/step, %.0f MLUPS, %.0f GB/s algorithmic, passes %s"
             % (name, r["ms_per_step"], r["mlups"], r["algo_gbs"], r["pass_ms"]))
@@ -361,7 +369,7 @@ def main():
             "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE)",
             "kernel": ("collide pass (z-marching fused_kernel, phase field from the phase pass)"
                        if head["kernel"] == 1 else
-                       "one-read collide tile (single_kernel; phase field assembled by assemble_kernel)"),
+                       "one-read tile (lean_kernel; face-site phase field completed by assemble_kernel)"),
             "algo_bytes_per_site": ALGO_BYTES[st], "sites_per_launch": w.sites,
             "kernel_ms": round(dom_ms, 4)}
 
@@ -375,10 +383,13 @@ def main():
         kort = korteweg_leg(w, stream)
         log("korteweg: %s" % kort)
 
-    serve_out = None
+    serve_out = sat_out = None
     if args.serve_jobs > 0:
         serve_out = serving(reqs, prep, args.serve_rate, args.serve_steps, 0.8 * 288)
         log("serving: %s" % serve_out)
+        if sat_reqs is not None:
+            sat_out = serving(sat_reqs, prep, args.serve_sat_rate, args.serve_steps, 0.8 * 288)
+            log("serving, batch kept full: %s" % sat_out)
 
     cpu = None
     if not args.no_cpu:
@@ -410,10 +421,12 @@ def main():
         "variants": {k: {"mlups": round(v["mlups"], 1), "ms_per_step": round(v["ms_per_step"], 4),
                          "algo_gbs": round(v["algo_gbs"], 1),
                          "pass_ms": [round(x, 4) for x in v["pass_ms"]],
+                         "tile_algo_gbs": round(v["tile_algo_gbs"], 1),
                          "finite": v["finite"]} for k, v in results.items()},
         "roofline": roof,
         "korteweg": kort,
         "serving": serve_out,
+        "serving_saturated": sat_out,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
