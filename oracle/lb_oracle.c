@@ -35,7 +35,10 @@
  *     the same velocity shift F/rho in the EDM source.
  *   - F_rep: delta_I = |G|, n = -G/|G| (outward normal), so F_rep = A_h G;
  *     h is the first k in 1..K at which the ray sample x + round(k n) is an
- *     interface site whose gradient opposes G(x).
+ *     interface site whose gradient opposes G(x).  The sampling is pinned by
+ *     brute-force scans of films whose normal lies along a lattice axis, a
+ *     face diagonal or the body diagonal; for other normals its parity is
+ *     unpinned (checked only against the GPU path).
  *   - the colour gradient at a wall reads the mirror site across the
  *     halfway wall plane (neutral wetting).
  *

@@ -212,3 +212,91 @@ def test_near_contact_ignores_an_isolated_droplet():
     phi = (w.rho_r - w.rho_b) / (w.rho_r + w.rho_b)
     G = O.phase_gradient(prm, phi)
     assert np.all(O.nearcontact(prm, G) == 0.0)
+
+
+def _diagonal_film_force_brute(phi_u, g_u, strength, K, hmin, g_iface):
+    """Special case of a film whose phase field depends on u = a + b only (a, b
+    two lattice axes, periodic, equal extents n): G lies along e_a + e_b, its
+    two components equal (g_u at each u), so the outward normal is
+    -sign(g_u)(e_a + e_b)/sqrt(2) and ray sample k sits at
+    u - 2 round(k / sqrt 2) sign(g_u) (C rounding: halves away from zero)."""
+    n = len(phi_u)
+    gm = np.abs(g_u) * np.sqrt(2.0)           # |G| with two equal components
+    F = np.zeros(n)
+    for u in range(n):
+        if gm[u] < g_iface:
+            continue
+        s = 1 if g_u[u] > 0 else -1
+        for k in range(1, K + 1):
+            off = int(np.floor(k / np.sqrt(2.0) + 0.5))
+            v = (u - 2 * off * s) % n
+            if gm[v] >= g_iface and g_u[v] * g_u[u] < 0:
+                amp = strength if k <= hmin else strength * (hmin / k) ** 3
+                F[u] = amp * g_u[u]
+                break
+    return F
+
+
+@pytest.mark.parametrize("axes", [(2, 1), (2, 0), (1, 0)])
+@pytest.mark.parametrize("K,hmin", [(2, 2.0), (4, 2.0)])
+def test_near_contact_on_a_diagonal_film_matches_brute_force(axes, K, hmin):
+    # two slabs of red and a thin blue film, constant along the lattice
+    # diagonal of two axes: the probe's rays run along that diagonal, so its
+    # sampling of off-axis normals (the rounding of k n in two components at
+    # once) reduces to a scan in u = a + b
+    n = 24
+    a, b = axes                                     # array axes (z = 0, y = 1, x = 2)
+    shape = [3, 3, 3]
+    shape[a] = shape[b] = n
+    u = np.arange(n, dtype=np.float64)
+    phi_u = np.maximum(np.tanh((5 - np.abs(u - 6)) / 2), np.tanh((5 - np.abs(u - 18.5)) / 2))
+    idx = np.indices(shape)
+    field = phi_u[(idx[a] + idx[b]) % n]
+    prm = O.Params(nx=shape[2], ny=shape[1], nz=shape[0], nc_strength=0.02, nc_range=K, nc_hmin=hmin,
+                   eps_g=1e-12)
+    G = O.phase_gradient(prm, field)
+    comp = {2: 0, 1: 1, 0: 2}                       # array axis -> component of G (x, y, z)
+    ga, gb = G[comp[a]], G[comp[b]]
+    assert np.allclose(ga, gb, atol=1e-15)          # G along the diagonal
+    other = 3 - comp[a] - comp[b]
+    assert np.abs(G[other]).max() < 1e-15
+    sel = [1, 1, 1]
+    sel[b] = 0                                      # the line a + 0 runs through every u
+    line = tuple(slice(None) if k == a else sel[k] for k in range(3))
+    g_u = ga[line]
+    Fn = O.nearcontact(prm, G)
+    Fb = _diagonal_film_force_brute(phi_u, g_u, 0.02, K, hmin, 0.05)
+    assert np.count_nonzero(Fb) > 0                 # the film is detected
+    assert np.allclose(Fn[comp[a]][line], Fb, atol=1e-17)
+    assert np.allclose(Fn[comp[b]][line], Fb, atol=1e-17)
+    assert np.abs(Fn[other]).max() < 1e-18
+
+
+@pytest.mark.parametrize("K,hmin", [(2, 2.0), (4, 2.0)])
+def test_near_contact_on_a_body_diagonal_film_matches_brute_force(K, hmin):
+    # the same along the body diagonal: phi depends on u = x + y + z, G has
+    # three equal components, ray sample k sits at u - 3 round(k / sqrt 3) sign
+    n = 24
+    u = np.arange(n, dtype=np.float64)
+    phi_u = np.maximum(np.tanh((5 - np.abs(u - 6)) / 2), np.tanh((5 - np.abs(u - 18.5)) / 2))
+    z, y, x = np.indices((n, n, n))
+    field = phi_u[(x + y + z) % n]
+    prm = O.Params(nx=n, ny=n, nz=n, nc_strength=0.02, nc_range=K, nc_hmin=hmin, eps_g=1e-12)
+    G = O.phase_gradient(prm, field)
+    assert np.allclose(G[0], G[1], atol=1e-15) and np.allclose(G[0], G[2], atol=1e-15)
+    g_u = G[0][0, 0, :]                             # the line y = z = 0 runs through every u
+    gm = np.abs(g_u) * np.sqrt(3.0)
+    Fb = np.zeros(n)
+    for k0 in range(n):
+        if gm[k0] < 0.05:
+            continue
+        s = 1 if g_u[k0] > 0 else -1
+        for k in range(1, K + 1):
+            v = (k0 - 3 * int(np.floor(k / np.sqrt(3.0) + 0.5)) * s) % n
+            if gm[v] >= 0.05 and g_u[v] * g_u[k0] < 0:
+                Fb[k0] = (0.02 if k <= hmin else 0.02 * (hmin / k) ** 3) * g_u[k0]
+                break
+    Fn = O.nearcontact(prm, G)
+    assert np.count_nonzero(Fb) > 0
+    for c in range(3):
+        assert np.allclose(Fn[c][0, 0, :], Fb, atol=1e-17)
