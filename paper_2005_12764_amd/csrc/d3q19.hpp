@@ -61,6 +61,20 @@ struct Coeffs {
     R g_sc;                // Shan-Chen coupling G_C
 };
 
+// c_i . a for a lattice velocity c_i (components -1, 0, 1): the sum of the
+// non-zero components' terms only (a product by a zero component is not
+// dropped by the compiler, since 0 * a is not 0 for every float a).
+template <typename R>
+__device__ __forceinline__ R cdot3(int i, R ax, R ay, R az) {
+    using L = Lattice;
+    R v = R(0);
+    bool any = false;
+    if (L::cx[i]) { v = L::cx[i] > 0 ? ax : -ax; any = true; }
+    if (L::cy[i]) { const R b = L::cy[i] > 0 ? ay : -ay; v = any ? v + b : b; any = true; }
+    if (L::cz[i]) { const R b = L::cz[i] > 0 ? az : -az; v = any ? v + b : b; }
+    return v;
+}
+
 // Reciprocal and reciprocal square root.  FP32: the hardware estimates
 // (v_rcp_f32, v_rsq_f32, within 1 ulp), used where an FP32 result only feeds
 // further rounding-level arithmetic; FP64: correctly rounded.
@@ -147,9 +161,9 @@ __device__ __forceinline__ void collide(R (&t)[Q], R (&d)[Q], R gx, R gy, R gz, 
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const R w = weight<R>(i);
-        const R cu = R(L::cx[i]) * ux + R(L::cy[i]) * uy + R(L::cz[i]) * uz;
-        const R cd = R(L::cx[i]) * dx + R(L::cy[i]) * dy + R(L::cz[i]) * dz;
-        const R cs = R(L::cx[i]) * sx + R(L::cy[i]) * sy + R(L::cz[i]) * sz;
+        const R cu = cdot3<R>(i, ux, uy, uz);
+        const R cd = cdot3<R>(i, dx, dy, dz);
+        const R cs = cdot3<R>(i, sx, sy, sz);
         const R q = R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu;                // f^eq/(w rho) - 1
         const R de = w * (R(3) * cd + R(4.5) * cd * cs - R(1.5) * ds);        // source / rho_k
         // total: BGK toward rho w (1 + q) (deviation w (drho + rho q)) plus rho de
@@ -157,7 +171,7 @@ __device__ __forceinline__ void collide(R (&t)[Q], R (&d)[Q], R gx, R gy, R gz, 
         const R tp = t[i] - omega * (t[i] - teq) + rho * de;
         // (the components' own relaxation only enters through this total:
         // recolouring redistributes the colour from rho_r/rho and f*)
-        const R cn = R(L::cx[i]) * nx + R(L::cy[i]) * ny + R(L::cz[i]) * nz;   // c_i . n
+        const R cn = cdot3<R>(i, nx, ny, nz);   // c_i . n
         const R ts = tp + pa * (w * cn * cn - bpert<R>(i));                    // perturbation
         // recolouring: f^r = x_r f* + rec, f^b = x_b f* - rec, f* = w + t*
         const R rec = seg * w * cn * inv_clen<R>(i);
@@ -224,14 +238,14 @@ __device__ __forceinline__ void collide_sc(R (&t)[Q], R (&d)[Q], R bx, R by, R b
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const R w = weight<R>(i);
-        const R cu = R(L::cx[i]) * ux + R(L::cy[i]) * uy + R(L::cz[i]) * uz;
+        const R cu = cdot3<R>(i, ux, uy, uz);
         const R q = R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu;
         const R teq = w * (drho + rho * q);          // f^eq(rho_r) + f^eq(rho_b) - w
         const R deq = w * dif * (R(1) + q);          // f^eq(rho_r) - f^eq(rho_b)
-        const R cdR = R(L::cx[i]) * Rx + R(L::cy[i]) * Ry + R(L::cz[i]) * Rz;
-        const R csR = R(L::cx[i]) * sRx + R(L::cy[i]) * sRy + R(L::cz[i]) * sRz;
-        const R cdB = R(L::cx[i]) * Bx + R(L::cy[i]) * By + R(L::cz[i]) * Bz;
-        const R csB = R(L::cx[i]) * sBx + R(L::cy[i]) * sBy + R(L::cz[i]) * sBz;
+        const R cdR = cdot3<R>(i, Rx, Ry, Rz);
+        const R csR = cdot3<R>(i, sRx, sRy, sRz);
+        const R cdB = cdot3<R>(i, Bx, By, Bz);
+        const R csB = cdot3<R>(i, sBx, sBy, sBz);
         const R SR = rr * w * (R(3) * cdR + R(4.5) * cdR * csR - R(1.5) * dsR);
         const R SB = rb * w * (R(3) * cdB + R(4.5) * cdB * csB - R(1.5) * dsB);
         t[i] = t[i] - omega * (t[i] - teq) + (SR + SB);
@@ -256,7 +270,7 @@ __device__ __forceinline__ void from_shifted(int i, R t, R d, R& fr, R& fb) {
 template <typename R>
 __device__ __forceinline__ R feq_unit(int i, R ux, R uy, R uz) {
     using L = Lattice;
-    const R cu = R(L::cx[i]) * ux + R(L::cy[i]) * uy + R(L::cz[i]) * uz;
+    const R cu = cdot3<R>(i, ux, uy, uz);
     const R uu = ux * ux + uy * uy + uz * uz;
     return weight<R>(i) * (R(1) + R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu);
 }
