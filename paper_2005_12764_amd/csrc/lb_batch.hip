@@ -1,8 +1,9 @@
 // lb_batch.hip -- many independent lattices (jobs) advanced together: each
-// step is one persistent assembly launch and one persistent tile launch, each
-// walking a work list of (job, item) pairs with the same code as the one-read
-// step of a single lattice (assemble_site, lean_tile), then a one-thread tick;
-// steps are replayed from a captured HIP graph.
+// step is one persistent assembly launch and two persistent tile launches
+// (jobs without walls, jobs with walls), each walking a work list of
+// (job, item) pairs with the same code as the one-read step of a single
+// lattice (assemble_site, lean_tile), then a one-thread tick; steps are
+// replayed from a captured HIP graph.
 //
 // Each job has a window [first, last) of global steps.  A device counter holds
 // the global step; the step kernels read it, skip jobs outside their window
@@ -116,15 +117,16 @@ __device__ __forceinline__ bool job_live(const BatchJob<R>& J, long long gs) {
     return J.active && gs >= J.first && gs < J.last;
 }
 
-// Assembly: phi of the face sites of every live job's current state.
-// n_items[0] tile items come first in the list, then n_items[1] assembly items.
+// Assembly: phi of the face sites of every live job's current state.  The
+// work list holds n_items[0] tile items of jobs without walls, then
+// n_items[1] tile items of jobs with walls, then n_items[2] assembly items.
 template <typename R, typename S, int TY>
 __global__ __launch_bounds__(kAsmThreads) void batch_assemble_kernel(const BatchJob<R>* __restrict__ jobs,
                                                                      const WorkItem* __restrict__ items,
                                                                      const int* __restrict__ n_items,
                                                                      const long long* __restrict__ gstep) {
     using B = BatchStorage<S>;
-    const int n0 = n_items[0], n = n_items[1];
+    const int n0 = n_items[0] + n_items[1], n = n_items[2];
     const long long gs = *gstep;
     for (int w = persistent_start(); w < n; w += gridDim.x) {
         const WorkItem it = items[n0 + w];
@@ -144,8 +146,9 @@ __host__ __device__ constexpr size_t batch_lds_bytes() {
 }
 
 // Tiles: collide, stream and gather the next state's phase sums of every
-// live job's tile items.
-template <typename S, int TY>
+// live job's tile items, jobs with walls (W) or without them (the two tile
+// variants in one kernel would hold the registers of both).
+template <typename S, int TY, bool W>
 __global__ __launch_bounds__(kTX * TY) void batch_tile_kernel(const BatchJob<typename S::R>* __restrict__ jobs,
                                                               const WorkItem* __restrict__ items,
                                                               const int* __restrict__ n_items,
@@ -159,10 +162,10 @@ __global__ __launch_bounds__(kTX * TY) void batch_tile_kernel(const BatchJob<typ
     off += S::ring_bytes(TY);
     R* xch = reinterpret_cast<R*>(lds_raw + off);
     Part2<R>* vs = reinterpret_cast<Part2<R>*>(lds_raw + off + lean_xch_bytes<R, TY>());
-    const int n = n_items[0];
+    const int first = W ? n_items[0] : 0, n = n_items[W ? 1 : 0];
     const long long gs = *gstep;
     for (int w = persistent_start(); w < n; w += gridDim.x) {
-        const WorkItem it = items[w];
+        const WorkItem it = items[first + w];
         const BatchJob<R>& J = jobs[it.slot];
         if (!job_live(J, gs)) continue;  // uniform over the workgroup
         const int par = (int)((gs - J.first) & 1);
@@ -173,12 +176,8 @@ __global__ __launch_bounds__(kTX * TY) void batch_tile_kernel(const BatchJob<typ
         const int za = chunk * J.fs.TZ, zb = min(za + J.fs.TZ, g.nz);
         Part2<R>* const pin = (Part2<R>*)J.part[par];
         Part2<R>* const pout = (Part2<R>*)J.part[par ^ 1];
-        if (g.wx || g.wy || g.wz)
-            lean_tile<S, TY, kBatchH, true>(g, st, J.c, ringb, xch, vs, x0, y0, za, zb, phi_of<kTX>(pin, g), pout,
-                                            phi_of<kTX>(pout, g));
-        else
-            lean_tile<S, TY, kBatchH, false>(g, st, J.c, ringb, xch, vs, x0, y0, za, zb, phi_of<kTX>(pin, g), pout,
-                                             phi_of<kTX>(pout, g));
+        lean_tile<S, TY, kBatchH, W>(g, st, J.c, ringb, xch, vs, x0, y0, za, zb, phi_of<kTX>(pin, g), pout,
+                                     phi_of<kTX>(pout, g));
         __syncthreads();  // the next item restages every LDS ring
     }
 }
@@ -283,7 +282,7 @@ struct lb_batch_t {
     std::vector<HostJob> jobs;
     void* d_jobs = nullptr;     // BatchJob<R>[max_jobs]
     WorkItem* d_items = nullptr;  // tile items, then assembly items
-    int* d_nitems = nullptr;      // [2]: tile items, assembly items
+    int* d_nitems = nullptr;      // [3]: tile items without walls, with walls, assembly items
     long long* d_gstep = nullptr;
     int items_cap = 0;
     long long gstep = 0;        // host mirror of the device counter
@@ -362,14 +361,20 @@ int upload_desc(lb_batch_t* b, int slot) {
     return rc;
 }
 
+bool has_walls(const lb_params& p) { return p.bc[0] || p.bc[1] || p.bc[2]; }
+
 int upload_items(lb_batch_t* b) {
     std::vector<WorkItem> items;
-    for (int s = 0; s < b->max_jobs; ++s) {
-        const HostJob& h = b->jobs[s];
-        if (!h.used) continue;
-        for (int k = 0; k < h.fs.nblocks; ++k) items.push_back(WorkItem{s, k});
+    int counts[3] = {0, 0, 0};
+    for (int pass = 0; pass < 2; ++pass) {
+        // tile items of the jobs without walls, then of those with walls
+        for (int s = 0; s < b->max_jobs; ++s) {
+            const HostJob& h = b->jobs[s];
+            if (!h.used || has_walls(h.p) != (pass == 1)) continue;
+            for (int k = 0; k < h.fs.nblocks; ++k) items.push_back(WorkItem{s, k});
+        }
+        counts[pass] = (int)items.size() - (pass ? counts[0] : 0);
     }
-    int counts[2] = {(int)items.size(), 0};
     for (int s = 0; s < b->max_jobs; ++s) {
         const HostJob& h = b->jobs[s];
         if (!h.used) continue;
@@ -377,7 +382,7 @@ int upload_items(lb_batch_t* b) {
         const int runs = (f.row_sites + f.edge_sites + kAsmThreads - 1) / kAsmThreads;
         for (int k = 0; k < runs; ++k) items.push_back(WorkItem{s, k});
     }
-    counts[1] = (int)items.size() - counts[0];
+    counts[2] = (int)items.size() - counts[0] - counts[1];
     if ((int)items.size() > b->items_cap) {
         // grow the work list; the graph holds its pointer, so drop the graph
         if (b->exec) (void)hipGraphExecDestroy(b->exec);
@@ -401,9 +406,9 @@ int upload_items(lb_batch_t* b) {
     return rc;
 }
 
-template <typename S, int TY>
+template <typename S, int TY, bool W>
 const void* tile_kernel_of() {
-    return reinterpret_cast<const void*>(batch_tile_kernel<S, TY>);
+    return reinterpret_cast<const void*>(batch_tile_kernel<S, TY, W>);
 }
 
 template <typename S, int TY>
@@ -414,7 +419,11 @@ int launch_batch_ty(lb_batch_t* b) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return bfail(LB_EDEVICE, std::string("batch_assemble_kernel: ") + hipGetErrorString(e));
     const size_t lds = batch_lds_bytes<S, TY>();
-    hipLaunchKernelGGL((batch_tile_kernel<S, TY>), dim3(b->grid), dim3(kTX * TY), lds, b->stream,
+    hipLaunchKernelGGL((batch_tile_kernel<S, TY, false>), dim3(b->grid), dim3(kTX * TY), lds, b->stream,
+                       (const BatchJob<R>*)b->d_jobs, b->d_items, b->d_nitems, b->d_gstep);
+    e = hipGetLastError();
+    if (e != hipSuccess) return bfail(LB_EDEVICE, std::string("batch_tile_kernel: ") + hipGetErrorString(e));
+    hipLaunchKernelGGL((batch_tile_kernel<S, TY, true>), dim3(b->grid), dim3(kTX * TY), lds, b->stream,
                        (const BatchJob<R>*)b->d_jobs, b->d_items, b->d_nitems, b->d_gstep);
     e = hipGetLastError();
     if (e != hipSuccess) return bfail(LB_EDEVICE, std::string("batch_tile_kernel: ") + hipGetErrorString(e));
@@ -439,15 +448,19 @@ int batch_step_once(lb_batch_t* b) {
     return bfail(LB_EINVAL, "unknown storage");
 }
 
-// The tile kernel of the batch (for its LDS opt-in and occupancy).
+// A tile kernel of the batch (for its LDS opt-in and occupancy).
+template <bool W>
 const void* batch_tile_kernel_of(int storage, int TY) {
     switch (storage) {
-        case LB_STORE_F64: return TY == 4 ? tile_kernel_of<LeanRaw<double>, 4>() : tile_kernel_of<LeanRaw<double>, 8>();
-        case LB_STORE_F32: return TY == 4 ? tile_kernel_of<LeanRaw<float>, 4>() : tile_kernel_of<LeanRaw<float>, 8>();
-        case LB_STORE_F16: return TY == 4 ? tile_kernel_of<LeanSplit<__half>, 4>() : tile_kernel_of<LeanSplit<__half>, 8>();
+        case LB_STORE_F64:
+            return TY == 4 ? tile_kernel_of<LeanRaw<double>, 4, W>() : tile_kernel_of<LeanRaw<double>, 8, W>();
+        case LB_STORE_F32:
+            return TY == 4 ? tile_kernel_of<LeanRaw<float>, 4, W>() : tile_kernel_of<LeanRaw<float>, 8, W>();
+        case LB_STORE_F16:
+            return TY == 4 ? tile_kernel_of<LeanSplit<__half>, 4, W>() : tile_kernel_of<LeanSplit<__half>, 8, W>();
         default:
-            return TY == 4 ? tile_kernel_of<LeanSplit<__hip_bfloat16>, 4>()
-                           : tile_kernel_of<LeanSplit<__hip_bfloat16>, 8>();
+            return TY == 4 ? tile_kernel_of<LeanSplit<__hip_bfloat16>, 4, W>()
+                           : tile_kernel_of<LeanSplit<__hip_bfloat16>, 8, W>();
     }
 }
 
@@ -552,12 +565,16 @@ int lb_batch_create(int32_t max_jobs, int64_t arena_bytes, int32_t storage, int3
     b->tz = ts.tz > 0 ? ts.tz : 32;
     // the tile launch holds as many workgroups as are resident at once (LDS
     // beyond 64 KB needs the opt-in); the assembly launch 8 per CU
-    const void* kern = batch_tile_kernel_of(storage, b->ty);
     const size_t lds = batch_tile_lds(storage, b->ty);
-    int per_cu = 0;
+    int per_cu = 0, per_cu_w = 0;
+    const void* kern = batch_tile_kernel_of<false>(storage, b->ty);
+    const void* kern_w = batch_tile_kernel_of<true>(storage, b->ty);
     hipError_t he = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (he == hipSuccess)
-        he = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kTX * b->ty, lds);
+    if (he == hipSuccess) he = hipFuncSetAttribute(kern_w, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (he == hipSuccess) he = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kTX * b->ty, lds);
+    if (he == hipSuccess) he = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_w, kern_w, kTX * b->ty, lds);
+    // one grid for both variants: as many workgroups as are resident at once for either
+    per_cu = std::min(per_cu, per_cu_w);
     if (he != hipSuccess || per_cu < 1) {
         if (b->own_stream) (void)hipStreamDestroy(b->stream);
         delete b;
@@ -568,10 +585,10 @@ int lb_batch_create(int32_t max_jobs, int64_t arena_bytes, int32_t storage, int3
     int rc = LB_OK;
     if ((rc = bcheck(hipMalloc((void**)&b->arena_base, (size_t)arena_bytes), "hipMalloc arena")) ||
         (rc = bcheck(hipMalloc(&b->d_jobs, desc_size(storage) * max_jobs), "hipMalloc job table")) ||
-        (rc = bcheck(hipMalloc((void**)&b->d_nitems, 2 * sizeof(int)), "hipMalloc counts")) ||
+        (rc = bcheck(hipMalloc((void**)&b->d_nitems, 3 * sizeof(int)), "hipMalloc counts")) ||
         (rc = bcheck(hipMalloc((void**)&b->d_gstep, sizeof(long long)), "hipMalloc step counter")) ||
         (rc = bcheck(hipMemsetAsync(b->d_jobs, 0, desc_size(storage) * max_jobs, b->stream), "clear job table")) ||
-        (rc = bcheck(hipMemsetAsync(b->d_nitems, 0, 2 * sizeof(int), b->stream), "clear counts")) ||
+        (rc = bcheck(hipMemsetAsync(b->d_nitems, 0, 3 * sizeof(int), b->stream), "clear counts")) ||
         (rc = bcheck(hipMemsetAsync(b->d_gstep, 0, sizeof(long long), b->stream), "clear counter")) ||
         (rc = upload_items(b))) {
         lb_batch_destroy(b);
