@@ -177,7 +177,7 @@ __global__ __launch_bounds__(kTX * TY) void batch_tile_kernel(const BatchJob<typ
         Part2<R>* const pin = (Part2<R>*)J.part[par];
         Part2<R>* const pout = (Part2<R>*)J.part[par ^ 1];
         lean_tile<S, TY, kBatchH, W>(g, st, J.c, ringb, xch, vs, x0, y0, za, zb, phi_of<kTX>(pin, g), pout,
-                                     phi_of<kTX>(pout, g));
+                                     phi_of<kTX>(pout, g), 0);  // (batched jobs have no moving walls)
         __syncthreads();  // the next item restages every LDS ring
     }
 }

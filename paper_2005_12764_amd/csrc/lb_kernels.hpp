@@ -168,11 +168,22 @@ struct RawPop {
         d = R(f[(size_t)(Q + dir) * N + src]);
     }
 
+    // The site's own post-collision x_r - x_b = sum d_j / sum (w_j + t_j) from
+    // its stored values, summed in ascending direction.
+    template <typename R>
+    __device__ __forceinline__ R own_phase(int s) const {
+        R st = R(0), sd = R(0);
+        for (int j = 0; j < Q; ++j) {
+            st += weight<R>(j) + R(f[(size_t)j * N + s]);
+            sd += R(f[(size_t)(Q + j) * N + s]);
+        }
+        return sd / st;
+    }
     // Moving-wall terms of the reflected directions, shared between the
     // components by the site's own post-collision rho_k/rho.
     template <typename R>
     __device__ void add_wall_terms(const Geom& g, int s, int x, int y, int z, R (&t)[Q], R (&d)[Q]) const {
-        R st = R(0), sd = R(0);
+        R ph = R(0);
         bool have = false;
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
@@ -180,15 +191,12 @@ struct RawPop {
             (void)pull_source(g, i, x, y, z, s, dir);
             if (dir == i) continue;
             if (!have) {
-                for (int j = 0; j < Q; ++j) {
-                    st += weight<R>(j) + R(f[(size_t)j * N + s]);
-                    sd += R(f[(size_t)(Q + j) * N + s]);
-                }
+                ph = own_phase<R>(s);
                 have = true;
             }
             const R add = wall_term<R>(g, i, x, y, z);
             t[i] += add;
-            d[i] += add * (sd / st);   // add x_r - add x_b
+            d[i] += add * ph;   // add x_r - add x_b
         }
     }
     template <typename R>
@@ -313,6 +321,11 @@ struct SplitPop {
         decode<R>(i, dir, ra, rb, dev[(size_t)dir * N + src], t, d);
     }
 
+    // The site's own post-collision x_r - x_b: the phase of its record.
+    template <typename R>
+    __device__ __forceinline__ R own_phase(int s) const {
+        return R(rec[8 * (size_t)s + 4]);
+    }
     // Moving-wall terms of the reflected directions, shared by the site's own
     // post-collision phase phi (from its record): add x_r - add x_b.
     template <typename R>

@@ -212,6 +212,28 @@ struct LeanRaw {
                     d[i] = res_load(R(0), fi.r[(Q + o) / kResArrays], bx0, soff(Q + o, P.own_row));
                 }
             }
+            // moving walls: each reflected direction gains the wall term,
+            // shared between the components by the site's own post-collision
+            // phase (as RawPop::add_wall_terms)
+            const bool wyz = (g.wy && (P.yc == 0 || P.yc == g.ny - 1)) || (g.wz && (P.cz == 0 || P.cz == g.nz - 1));
+            if (g.moving && (wyz || ln.wall_xlo || ln.wall_xhi)) {
+                R st = R(0), sd = R(0);
+                for (int j = 0; j < Q; ++j) {
+                    st += weight<R>(j) + res_load(R(0), fi.r[j / kResArrays], bx0, soff(j, P.own_row));
+                    sd += res_load(R(0), fi.r[(Q + j) / kResArrays], bx0, soff(Q + j, P.own_row));
+                }
+                const R ph = sd / st;
+#pragma unroll
+                for (int i = 1; i < Q; ++i) {
+                    bool bb;
+                    (void)upstream_row<W>(g, P.yc, P.cz, L::cy[i], L::cz[i], bb);
+                    const bool rx = (L::cx[i] > 0 && ln.wall_xlo) || (L::cx[i] < 0 && ln.wall_xhi);
+                    if (!(bb || rx)) continue;
+                    const R add = wall_term<R>(g, i, (int)ln.cx0, P.yc, P.cz);
+                    t[i] += add;
+                    d[i] += add * ph;
+                }
+            }
         }
     }
 
@@ -466,7 +488,7 @@ __device__ __forceinline__ void lean_tile(const Geom& g, const S& st, const Coef
                                           Part2<typename S::R>* __restrict__ vs, int x0, int y0, int za, int zb,
                                           const typename S::R* __restrict__ phi_in,
                                           Part2<typename S::R>* __restrict__ part_out,
-                                          typename S::R* __restrict__ phi_out) {
+                                          typename S::R* __restrict__ phi_out, int moving_next) {
     using L = Lattice;
     using R = typename S::R;
     constexpr int TX = kTX;
@@ -647,10 +669,25 @@ __device__ __forceinline__ void lean_tile(const Geom& g, const S& st, const Coef
                 }
             }
         }
-        // bounce-backs into this site: its own values, before the in-plane group
+        // bounce-backs into this site: its own values, before the in-plane
+        // group (off a moving wall, as the next pull reads them: plus the wall
+        // term, shared by the site's own post-collision phase; raw storage)
         {
             const bool ylo = W && g.wy && yc == 0, yhi = W && g.wy && yc == g.ny - 1;
             const bool zlo = W && g.wz && cz == 0, zhi = W && g.wz && cz == g.nz - 1;
+            R ph = R(0);
+            bool mv = false;
+            if constexpr (W && !S::split) {
+                mv = moving_next && (ylo || yhi || zlo || zhi || wall_xlo || wall_xhi);
+                if (mv) {
+                    R st = R(0), sd = R(0);
+                    for (int j = 0; j < Q; ++j) {
+                        st += weight<R>(j) + t[j];
+                        sd += d[j];
+                    }
+                    ph = sd / st;
+                }
+            }
 #pragma unroll
             for (int i = 1; i < Q; ++i) {
                 const bool ryz = (L::cy[i] > 0 && ylo) || (L::cy[i] < 0 && yhi) || (L::cz[i] > 0 && zlo) ||
@@ -658,8 +695,14 @@ __device__ __forceinline__ void lean_tile(const Geom& g, const S& st, const Coef
                 if constexpr (W) {
                     const bool rx = (L::cx[i] > 0 && wall_xlo) || (L::cx[i] < 0 && wall_xhi);
                     if (ryz || rx) {
-                        cur_rc += weight<R>(i) + t[L::opp[i]];
-                        cur_dn += d[L::opp[i]];
+                        R tv = t[L::opp[i]], dv = d[L::opp[i]];
+                        if (mv) {
+                            const R add = wall_term<R>(g, i, xc, yc, cz);
+                            tv += add;
+                            dv += add * ph;
+                        }
+                        cur_rc += weight<R>(i) + tv;
+                        cur_dn += dv;
                     }
                 } else {
                     if (ryz) {
@@ -782,7 +825,8 @@ __host__ __device__ constexpr size_t lean_lds_bytes() {
 template <typename S, int TY, int H, bool W>
 __global__ __launch_bounds__(kTX * TY) void lean_kernel(Geom g, S st, Coeffs<typename S::R> c, FusedShape fs,
                                                        const Part2<typename S::R>* __restrict__ part_in,
-                                                       Part2<typename S::R>* __restrict__ part_out) {
+                                                       Part2<typename S::R>* __restrict__ part_out,
+                                                       int moving_next) {
     using R = typename S::R;
     extern __shared__ unsigned char lds_raw[];
     R* ringb = reinterpret_cast<R*>(lds_raw);
@@ -797,7 +841,8 @@ __global__ __launch_bounds__(kTX * TY) void lean_kernel(Geom g, S st, Coeffs<typ
     int x0, y0, za, zb;
     tile_of_block(fs, kTX, g.nz, x0, y0, za, zb);
     lean_tile<S, TY, H, W>(g, st, c, ringb, xch, vs, x0, y0, za, zb,
-                           phi_of<kTX>(const_cast<Part2<R>*>(part_in), g), part_out, phi_of<kTX>(part_out, g));
+                           phi_of<kTX>(const_cast<Part2<R>*>(part_in), g), part_out, phi_of<kTX>(part_out, g),
+                           moving_next);
 }
 
 }  // namespace lbm

@@ -22,8 +22,11 @@ int launch_h(const LatticeView& v, const S& st, const Coeffs<typename S::R>& c, 
         if (e != hipSuccess)
             return set_error(LB_EDEVICE, (std::string("lean_kernel LDS: ") + hipGetErrorString(e)).c_str());
     }
+    // the next step's pull adds moving-wall terms even when this one (the
+    // first after a state was set) does not: the gathered sums follow the next
+    const int moving_next = make_geom(*v.p).moving;
     hipLaunchKernelGGL(kern, dim3(fs.nblocks), dim3(kTX * TY), lds, v.stream, v.g, st, c, fs,
-                       (const Part2<R>*)v.part_in, (Part2<R>*)v.part_out);
+                       (const Part2<R>*)v.part_in, (Part2<R>*)v.part_out, moving_next);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return set_error(LB_EDEVICE, (std::string("lean_kernel: ") + hipGetErrorString(e)).c_str());
     return LB_OK;

@@ -156,6 +156,8 @@ __global__ __launch_bounds__(256) void part_kernel(Geom g, Src src, int TZ, Part
     site_xyz(g, s, x, y, z);
     const OwnBox b = box_of<TX, TY>(g, TZ, x, y, z);
     R dn = R(0), rc = R(0);
+    R ph = R(0);  // own post-collision phase, for the moving-wall terms
+    bool have_ph = false;
 #pragma unroll
     for (int grp = 0; grp < 4; ++grp) {
 #pragma unroll
@@ -167,6 +169,18 @@ __global__ __launch_bounds__(256) void part_kernel(Geom g, Src src, int TZ, Part
             if (!refl && !b.has(x - L::cx[i], y - L::cy[i], z - L::cz[i])) continue;
             R t, d;
             src.template pull_one<R>(i, sr, dir, t, d);
+            if constexpr (Src::moving) {
+                // a reflection off a moving wall, as the pull adds it
+                if (refl && g.moving) {
+                    if (!have_ph) {
+                        ph = src.template own_phase<R>(s);
+                        have_ph = true;
+                    }
+                    const R add = wall_term<R>(g, i, x, y, z);
+                    t += add;
+                    d += add * ph;
+                }
+            }
             rc += weight<R>(i) + t;
             dn += d;
         }
