@@ -67,15 +67,14 @@ extern "C" {
 #define LB_STORE_BF16 3 /* as LB_STORE_F16 with bf16 deviations (no scale) */
 
 /* Kernel selection for lb_step. */
-#define LB_KERNEL_AUTO 0    /* the one-read step, except (two-pass) for 16-bit lattices with
-                               moving walls, the Shan-Chen model and lattices too large
-                               for its 32-bit buffer offsets */
+#define LB_KERNEL_AUTO 0    /* the one-read step, except (two-pass) for the Shan-Chen model
+                               and lattices too large for its 32-bit buffer offsets */
 #define LB_KERNEL_TWOPASS 1 /* phase-field pass, then collide-and-stream pass */
 #define LB_KERNEL_FUSED 2   /* one-read step: the collide-and-stream tiles also gather the
                                next phase field's sums, a light pass adds the terms
                                that cross tiles; every population is read once per
-                               step.  16-bit lattices with moving walls step with two
-                               passes after their first step. */
+                               step.  The first step of a 16-bit lattice with moving
+                               walls takes two passes. */
 
 /* Tile kinds of lb_set_tiles. */
 #define LB_TILES_PHASE 0    /* phase-field pass of two-pass steps (16-bit storage) */

@@ -379,10 +379,11 @@ int lb_init_droplets(lb_t* h, const double* centres, const double* radii, int32_
 // that ran.
 static int advance(lb_t* h, const StepEvents* t, int* used) {
     LatticeView v = view_of(h);
-    // 16-bit lattices with moving walls step with two passes (the one-read
-    // step carries wall terms for raw storage only)
-    const bool moving16 = h->g.moving && h->p.storage >= LB_STORE_F16;
-    const int kernel = (h->kernel == LB_KERNEL_FUSED && moving16) ? LB_KERNEL_TWOPASS : h->kernel;
+    // the first step of a 16-bit lattice with moving walls (from its raw
+    // initial state) takes two passes: the one-read kernel of that step does
+    // not gather the wall terms the next step's pull adds
+    const bool first16 = h->g.moving && h->pending;
+    const int kernel = (h->kernel == LB_KERNEL_FUSED && first16) ? LB_KERNEL_TWOPASS : h->kernel;
     int rc = launch_step(v, kernel, t);
     if (rc) return rc;
     if (h->pending) {
@@ -623,11 +624,6 @@ int lb_load_raw(lb_t* h, const void* src, int32_t on_device) {
 
 int64_t lb_step_count(const lb_t* h) { return h ? h->steps : -1; }
 
-int lb_kernel_in_use(const lb_t* h) {
-    if (!h) return LB_EINVAL;
-    // (16-bit lattices with moving walls step with two passes after their first step)
-    if (h->kernel == LB_KERNEL_FUSED && h->g.moving && h->p.storage >= LB_STORE_F16) return LB_KERNEL_TWOPASS;
-    return h->kernel;
-}
+int lb_kernel_in_use(const lb_t* h) { return h ? h->kernel : LB_EINVAL; }
 
 }  // extern "C"

@@ -372,16 +372,11 @@ int choose_kernel(const lb_params& p) {
     if (p.kernel == LB_KERNEL_TWOPASS) return LB_KERNEL_TWOPASS;
     if (p.kernel == LB_KERNEL_FUSED) return fits ? LB_KERNEL_FUSED : -1;
     // automatic: the one-read step (measured faster than two passes for raw
-    // and 16-bit storage); 16-bit lattices with moving walls take two passes
-    // (the one-read step carries wall terms for raw storage only), and so do
-    // the Shan-Chen model and lattices too large for 32-bit buffer offsets
-    bool moving = false;
-    for (int f = 0; f < 6; ++f)
-        for (int k = 0; k < 3; ++k) moving |= p.bc[f / 2] != 0 && p.wall_velocity[f][k] != 0.0;
+    // and 16-bit storage); the Shan-Chen model and lattices too large for
+    // 32-bit buffer offsets take two passes
     // (the one-read step's 32-bit byte offsets need 10 x sites x value size < 2^32)
     const bool small = (uint64_t)kResArrays * real_size(p) * (uint64_t)p.nx * p.ny * p.nz < ((uint64_t)1 << 32);
-    if ((moving && split_storage(p)) || !fits || !small || p.model != LB_MODEL_COLOUR_GRADIENT)
-        return LB_KERNEL_TWOPASS;
+    if (!fits || !small || p.model != LB_MODEL_COLOUR_GRADIENT) return LB_KERNEL_TWOPASS;
     return LB_KERNEL_FUSED;
 }
 

@@ -406,6 +406,23 @@ struct LeanSplit {
                     codec.decode(i, o, p0[own], p0[half() + own], dv, t[i], d[i]);
                 }
             }
+            // moving walls: each reflected direction gains the wall term,
+            // shared by the phase of the site's own record (as
+            // SplitPop::add_wall_terms)
+            const bool wyz = (g.wy && (P.yc == 0 || P.yc == g.ny - 1)) || (g.wz && (P.cz == 0 || P.cz == g.nz - 1));
+            if (g.moving && (wyz || ln.wall_xlo || ln.wall_xhi)) {
+                const float ph = p0[half() + own].x;
+#pragma unroll
+                for (int i = 1; i < Q; ++i) {
+                    bool bb;
+                    (void)upstream_row<W>(g, P.yc, P.cz, L::cy[i], L::cz[i], bb);
+                    const bool rx = (L::cx[i] > 0 && ln.wall_xlo) || (L::cx[i] < 0 && ln.wall_xhi);
+                    if (!(bb || rx)) continue;
+                    const R add = wall_term<R>(g, i, (int)ln.cx0, P.yc, P.cz);
+                    t[i] += add;
+                    d[i] += add * R(ph);
+                }
+            }
         }
     }
 
@@ -671,21 +688,25 @@ __device__ __forceinline__ void lean_tile(const Geom& g, const S& st, const Coef
         }
         // bounce-backs into this site: its own values, before the in-plane
         // group (off a moving wall, as the next pull reads them: plus the wall
-        // term, shared by the site's own post-collision phase; raw storage)
+        // term, shared by the site's own post-collision phase)
         {
             const bool ylo = W && g.wy && yc == 0, yhi = W && g.wy && yc == g.ny - 1;
             const bool zlo = W && g.wz && cz == 0, zhi = W && g.wz && cz == g.nz - 1;
             R ph = R(0);
             bool mv = false;
-            if constexpr (W && !S::split) {
+            if constexpr (W) {
                 mv = moving_next && (ylo || yhi || zlo || zhi || wall_xlo || wall_xhi);
                 if (mv) {
-                    R st = R(0), sd = R(0);
-                    for (int j = 0; j < Q; ++j) {
-                        st += weight<R>(j) + t[j];
-                        sd += d[j];
+                    if constexpr (S::split) {
+                        ph = tot.phi;  // the phase the site's record holds
+                    } else {
+                        R st = R(0), sd = R(0);
+                        for (int j = 0; j < Q; ++j) {
+                            st += weight<R>(j) + t[j];
+                            sd += d[j];
+                        }
+                        ph = sd / st;
                     }
-                    ph = sd / st;
                 }
             }
 #pragma unroll

@@ -320,18 +320,18 @@ def test_sheared_channel_with_droplets(storage, kernel):
     _parity(w, storage, 60, kernel)
 
 
-@pytest.mark.parametrize("storage", [W.F64, W.F32])
+@pytest.mark.parametrize("storage", [W.F64, W.F32, W.F16, W.BF16])
 def test_one_read_with_moving_walls_on_every_axis(storage):
     # walls on x, y and z, every face sliding its own way: the one-read step
     # adds the wall terms in its pulls and in the phase sums it gathers for
     # the next step (lanes next to the x walls, rows next to y and z walls);
     # against the oracle, and a run resumed from a checkpoint (its sums
-    # rebuilt from the state) bit for bit
+    # rebuilt from the state) bit for bit (16-bit: to FP32 rounding)
     w = W.two_droplets(n=(40, 20, 18), R=5, gap=2.0, A=0.01, nc_strength=0.03, nc_range=2)
     w.params["bc"] = (1, 1, 1)
     w.params["wall_velocity"] = ((0, 0.004, -0.002), (0, -0.003, 0.002), (0.005, 0, 0.001),
                                  (-0.004, 0, 0.003), (-0.01, 0.002, 0), (0.01, -0.001, 0))
-    e = _parity(w, storage, 40, lb.KERNEL_FUSED)
+    _parity(w, storage, 40, lb.KERNEL_FUSED)
     p = dict(w.params, storage=storage, kernel=lb.KERNEL_FUSED)
     with lb.Lattice(p) as A, lb.Lattice(p) as B:
         A.init(w.rho_r, w.rho_b).step(15)
@@ -342,7 +342,11 @@ def test_one_read_with_moving_walls_on_every_axis(storage):
         B.init(w.rho_r, w.rho_b).step(1)
         B.load_raw(ck)
         B.step(10)
-        assert np.array_equal(B.state(), straight)
+        if storage >= W.F16:
+            # as test_single_pass_resume_is_bitwise: 16-bit resume to FP32 rounding
+            assert state_errors(B.state(), straight)["worst"] < 1e-6
+        else:
+            assert np.array_equal(B.state(), straight)
 
 
 def test_sheared_channel_16bit():
