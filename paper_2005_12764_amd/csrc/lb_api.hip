@@ -120,9 +120,9 @@ Geom make_geom(const lb_params& p) {
 
 size_t pop_bytes(int storage, size_t N) {
     switch (storage) {
-        case LB_STORE_F64: return 2 * Q * N * sizeof(double);
-        case LB_STORE_F32: return 2 * Q * N * sizeof(float);
-        default: return 8 * N * sizeof(float) + Q * N * 2;
+        case LB_STORE_F64: return 2 * Q * raw_stride(N) * sizeof(double);
+        case LB_STORE_F32: return 2 * Q * raw_stride(N) * sizeof(float);
+        default: return 8 * N * sizeof(float) + Q * dev_stride(N) * 2;
     }
 }
 

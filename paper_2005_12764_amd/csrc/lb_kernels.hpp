@@ -136,10 +136,33 @@ __device__ __forceinline__ R wall_term(const Geom& g, int i, int x, int y, int z
 // site's post-collision populations in place (aligned, coalesced).
 // ---------------------------------------------------------------------------
 
-// Raw storage [2][19][N] of type T in shifted variables: component 0 holds
-// t_i = f^r_i + f^b_i - w_i, component 1 holds d_i = f^r_i - f^b_i.  MW: the
-// lattice has moving walls (a separate instantiation, so resting-wall kernels
-// carry none of that code).
+// Raw storage of type T in shifted variables, t_i = f^r_i + f^b_i - w_i and
+// d_i = f^r_i - f^b_i, as 19 arrays of (t_i, d_i) pairs: a direction's values
+// of one site are 2 sizeof(T) contiguous bytes, so a pull or a store of a
+// site moves 19 streams of pairs rather than 38 streams of single values.
+// Consecutive arrays start raw_stride(N) pairs apart: the kRawPad unused pairs
+// after each array keep the 19 streams of a site off a common power-of-two
+// stride (which maps them onto the same HBM channels).
+constexpr int kRawPad = 32;
+__host__ __device__ constexpr size_t raw_stride(size_t N) { return N + kRawPad; }
+template <typename T>
+struct RawPair {
+    typedef T type __attribute__((ext_vector_type(2)));
+};
+template <typename T>
+__device__ __forceinline__ typename RawPair<T>::type raw_pair(const T* f, size_t N, int i, int s) {
+    return *reinterpret_cast<const typename RawPair<T>::type*>(f + 2 * ((size_t)i * raw_stride(N) + s));
+}
+template <typename T>
+__device__ __forceinline__ void raw_put(T* f, size_t N, int i, int s, T t, T d) {
+    typename RawPair<T>::type v;
+    v.x = t;
+    v.y = d;
+    *reinterpret_cast<typename RawPair<T>::type*>(f + 2 * ((size_t)i * raw_stride(N) + s)) = v;
+}
+
+// Raw storage policy.  MW: the lattice has moving walls (a separate
+// instantiation, so resting-wall kernels carry none of that code).
 template <typename T, bool MW = false>
 struct RawPop {
     T* f;
@@ -152,8 +175,9 @@ struct RawPop {
         for (int i = 0; i < Q; ++i) {
             int dir;
             const int src = pull_source(g, i, x, y, z, s, dir);
-            t[i] = R(f[(size_t)dir * N + src]);
-            d[i] = R(f[(size_t)(Q + dir) * N + src]);
+            const auto v = raw_pair(f, N, dir, src);
+            t[i] = R(v.x);
+            d[i] = R(v.y);
         }
         if constexpr (MW) {
             if (g.moving) add_wall_terms<R>(g, s, x, y, z, t, d);
@@ -164,8 +188,9 @@ struct RawPop {
     template <typename R>
     __device__ __forceinline__ void pull_one(int i, int src, int dir, R& t, R& d) const {
         (void)i;
-        t = R(f[(size_t)dir * N + src]);
-        d = R(f[(size_t)(Q + dir) * N + src]);
+        const auto v = raw_pair(f, N, dir, src);
+        t = R(v.x);
+        d = R(v.y);
     }
 
     // The site's own post-collision x_r - x_b = sum d_j / sum (w_j + t_j) from
@@ -174,8 +199,9 @@ struct RawPop {
     __device__ __forceinline__ R own_phase(int s) const {
         R st = R(0), sd = R(0);
         for (int j = 0; j < Q; ++j) {
-            st += weight<R>(j) + R(f[(size_t)j * N + s]);
-            sd += R(f[(size_t)(Q + j) * N + s]);
+            const auto v = raw_pair(f, N, j, s);
+            st += weight<R>(j) + R(v.x);
+            sd += R(v.y);
         }
         return sd / st;
     }
@@ -204,8 +230,10 @@ struct RawPop {
                                           const SiteTotals<R>&) const {
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            __builtin_nontemporal_store(T(t[i]), &f[(size_t)i * N + s]);
-            __builtin_nontemporal_store(T(d[i]), &f[(size_t)(Q + i) * N + s]);
+            typename RawPair<T>::type v;
+            v.x = T(t[i]);
+            v.y = T(d[i]);
+            __builtin_nontemporal_store(v, reinterpret_cast<typename RawPair<T>::type*>(f + 2 * ((size_t)i * raw_stride(N) + s)));
         }
     }
     // Store, and replace t, d by the values a later pull reads.
@@ -254,14 +282,17 @@ __device__ __forceinline__ float cdot(int i, float sg, float ax, float ay, float
 // 16-bit moment-split storage.  Per site, 8 FP32 values rec[N][8] (two
 // 16-byte vectors per site) of the post-collision state: density - 1, the
 // momentum term J = 3 (j + F) of the equilibrium (3), the phase
-// phi = x_r - x_b and the recolouring vector (3); per direction dev[19][N]:
+// phi = x_r - x_b and the recolouring vector (3); per direction an array dev_i:
 // the total post-collision population's deviation t_i from the reference
 // w_i (drho + c_i . J) -- the equilibrium to first order in the velocity --
 // times `scale`, in 16 bits (the second-order part of the equilibrium, of
 // order u^2, is carried by the deviation with the non-equilibrium part).  The
 // colour difference of direction i is phi (w_i + t_i) + 2 w_i (c_i . v)/|c_i|,
-// exactly the form recolouring produces, so colour is carried in FP32.  MW as
-// for RawPop.
+// exactly the form recolouring produces, so colour is carried in FP32.  The
+// deviation arrays start dev_stride(N) values apart (kDevPad unused values
+// after each, for the reason of raw_stride).  MW as for RawPop.
+constexpr int kDevPad = 128;
+__host__ __device__ constexpr size_t dev_stride(size_t N) { return N + kDevPad; }
 template <typename H, bool MW = false>
 struct SplitPop {
     float* rec;
@@ -306,7 +337,7 @@ struct SplitPop {
             const int src = nbr_source(g, nb, i, d);
             const f4 ra = *reinterpret_cast<const f4*>(rec + 8 * (size_t)src);
             const f4 rb = *reinterpret_cast<const f4*>(rec + 8 * (size_t)src + 4);
-            decode<R>(i, d, ra, rb, dev[(size_t)d * N + src], t[i], d_[i]);
+            decode<R>(i, d, ra, rb, dev[(size_t)d * dev_stride(N) + src], t[i], d_[i]);
         }
         if constexpr (MW) {
             if (g.moving) add_wall_terms<R>(g, s, x, y, z, rec[8 * (size_t)s + 4], t, d_);
@@ -318,7 +349,7 @@ struct SplitPop {
     __device__ __forceinline__ void pull_one(int i, int src, int dir, R& t, R& d) const {
         const f4 ra = *reinterpret_cast<const f4*>(rec + 8 * (size_t)src);
         const f4 rb = *reinterpret_cast<const f4*>(rec + 8 * (size_t)src + 4);
-        decode<R>(i, dir, ra, rb, dev[(size_t)dir * N + src], t, d);
+        decode<R>(i, dir, ra, rb, dev[(size_t)dir * dev_stride(N) + src], t, d);
     }
 
     // The site's own post-collision x_r - x_b: the phase of its record.
@@ -359,7 +390,7 @@ struct SplitPop {
             const bool bb = (d != i);
             const f4* pl = bb ? ring[1] : ring[1 - L::cz[i]];
             const int pos = bb ? (ly * LXR + lx) : ((ly - L::cy[i]) * LXR + lx - L::cx[i]);
-            decode<R>(i, d, pl[pos], pl[half + pos], dev[(size_t)d * N + src], t[i], d_[i]);
+            decode<R>(i, d, pl[pos], pl[half + pos], dev[(size_t)d * dev_stride(N) + src], t[i], d_[i]);
         }
         if constexpr (MW) {
             const float phi_own = ring[1][half + ly * LXR + lx].x;
@@ -390,7 +421,7 @@ struct SplitPop {
             const float X = excess(i, 1.0f, ra);
             // deviation of f*_i - w_i = t_i from w_i X
             const H h = Half<H>::from_f((float(t[i]) - weight<float>(i) * X) * scale);
-            dev[(size_t)i * N + s] = h;
+            dev[(size_t)i * dev_stride(N) + s] = h;
             float tt, dd;
             finish(i, 1.0f, X, rb, h, tt, dd);
             t[i] = R(tt);
@@ -571,8 +602,7 @@ __global__ __launch_bounds__(256) void init_raw_kernel(Geom g, T* __restrict__ f
         const double q = 3.0 * cu + 4.5 * cu * cu - 1.5 * uu;
         const double w = weight<double>(d);
         const double a = double(rr[t]), b = double(rb[t]);
-        f[(size_t)j * N + s] = T(w * ((a + b - 1.0) + (a + b) * q));
-        f[(size_t)(Q + j) * N + s] = T((a - b) * w * (1.0 + q));
+        raw_put(f, N, j, s, T(w * ((a + b - 1.0) + (a + b) * q)), T((a - b) * w * (1.0 + q)));
     }
 }
 
@@ -596,8 +626,7 @@ __global__ __launch_bounds__(256) void import_raw_kernel(Geom g, T* __restrict__
         const int t = bb ? s : site_of(g, xt, yt, zt);
         const int d = bb ? L::opp[j] : j;
         const double a = double(fin[(size_t)d * N + t]), b = double(fin[(size_t)(Q + d) * N + t]);
-        f[(size_t)j * N + s] = T((a + b) - weight<double>(d));
-        f[(size_t)(Q + j) * N + s] = T(a - b);
+        raw_put(f, N, j, s, T((a + b) - weight<double>(d)), T(a - b));
     }
 }
 

@@ -6,8 +6,8 @@ namespace lbm {
 
 template <typename T>
 int launch_lean(const LatticeView& v, const T* fin, T* fout, const Coeffs<T>& c, const FusedShape& fs) {
-    // byte offsets within a buffer resource of ten arrays are 32-bit
-    if ((uint64_t)kResArrays * sizeof(T) * (uint64_t)v.g.N >= ((uint64_t)1 << 32))
+    // byte offsets within a buffer resource of five pair arrays are 32-bit
+    if ((uint64_t)kResArrays * sizeof(T) * (uint64_t)raw_stride((size_t)v.g.N) >= ((uint64_t)1 << 32))
         return set_error(LB_EINVAL, "lattice too large for the one-read step (10 x sites x value size >= 2^32)");
     const LeanRaw<T> st{fin, fout};
     switch (fs.TY) {

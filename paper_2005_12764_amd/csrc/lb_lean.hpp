@@ -31,25 +31,57 @@ __device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_rea
 __device__ __forceinline__ void in_vgpr(float& v) { asm volatile("" : "+v"(v)); }
 __device__ __forceinline__ void in_vgpr(double& v) { asm volatile("" : "+v"(v)); }
 
-// The 2 Q population arrays of a buffer as four buffer resources of up to
-// ten arrays each: a pull or store is then one buffer access with the row in
-// a scalar offset and the column in a per-lane offset, with no 64-bit address
-// arithmetic per access.  Each range is exact, so an access outside it reads
-// zero or is dropped.  Needs 10 N sizeof(T) < 2^32 (checked on the host).
+// The 19 (t_i, d_i) pair arrays of a raw buffer as four buffer resources of
+// up to five arrays (ten values per site) each: a pull or store is then one
+// buffer access of a pair with the row in a scalar offset and the column in a
+// per-lane offset, with no 64-bit address arithmetic per access.  Each range
+// is exact, so an access outside it reads zero or is dropped.  Needs
+// 10 raw_stride(N) sizeof(T) < 2^32 (checked on the host).
 constexpr int kResArrays = 10;
+constexpr int kResPairs = kResArrays / 2;
 constexpr unsigned kRsrcWord3 = 0x00020000;  // raw 32-bit buffer on gfx9-family targets
 template <typename T>
 struct PopRes {
     __amdgpu_buffer_rsrc_t r[4];
-    __device__ __forceinline__ PopRes(const T* f, unsigned N) {
+    // S: pairs from one array to the next (raw_stride(N))
+    __device__ __forceinline__ PopRes(const T* f, unsigned S) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const unsigned na = (unsigned)min(kResArrays, 2 * Q - k * kResArrays);
-            r[k] = __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(f) + (size_t)k * kResArrays * N, 0,
-                                                     (int)(na * N * (unsigned)sizeof(T)), (int)kRsrcWord3);
+            const unsigned np = (unsigned)min(kResPairs, Q - k * kResPairs);
+            r[k] = __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(f) + (size_t)k * kResArrays * S, 0,
+                                                     (int)(np * S * 2u * (unsigned)sizeof(T)), (int)kRsrcWord3);
         }
     }
 };
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+// (t, d) pair loads and non-temporal pair stores
+__device__ __forceinline__ void res_load_pair(float& t, float& d, __amdgpu_buffer_rsrc_t r, unsigned voff,
+                                              unsigned soff) {
+    const auto v = __builtin_bit_cast(RawPair<float>::type, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    t = v.x;
+    d = v.y;
+}
+__device__ __forceinline__ void res_load_pair(double& t, double& d, __amdgpu_buffer_rsrc_t r, unsigned voff,
+                                              unsigned soff) {
+    const auto v = __builtin_bit_cast(RawPair<double>::type, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+    t = v.x;
+    d = v.y;
+}
+__device__ __forceinline__ void res_store_pair(float t, float d, __amdgpu_buffer_rsrc_t r, unsigned voff,
+                                               unsigned soff) {
+    RawPair<float>::type v;
+    v.x = t;
+    v.y = d;
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 2);
+}
+__device__ __forceinline__ void res_store_pair(double t, double d, __amdgpu_buffer_rsrc_t r, unsigned voff,
+                                               unsigned soff) {
+    RawPair<double>::type v;
+    v.x = t;
+    v.y = d;
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, voff, soff, 2);
+}
 __device__ __forceinline__ float res_load(float, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
 }
@@ -140,7 +172,7 @@ struct LeanLane {
     int lane, ty;
 };
 
-// Raw storage: t_i and d_i in 2 Q arrays of T.  Pulls read each array at the
+// Raw storage: (t_i, d_i) pairs in Q arrays.  Pulls read each array at the
 // upstream row (scalar offset) and column (per lane); stores write in place.
 // The pulls load their values where they need them: loading them one plane
 // ahead takes 2 Q more vector registers, and the occupancy that costs (FP32:
@@ -162,16 +194,16 @@ struct LeanRaw {
     __device__ __forceinline__ void load(const Geom& g, int yc, int cz, const LeanLane& ln, T (&t)[Q],
                                          T (&d)[Q]) const {
         using L = Lattice;
-        unsigned Np = (unsigned)g.N;
-        asm volatile("" : "+s"(Np));
+        unsigned Sp = (unsigned)raw_stride((size_t)g.N);
+        asm volatile("" : "+s"(Sp));
         const T* fin_p = fin;
         asm volatile("" : "+s"(fin_p));  // resources rebuilt each plane (short-lived scalar registers)
-        const PopRes<T> fi(fin_p, Np);
-        constexpr unsigned SZ = (unsigned)sizeof(T);
+        const PopRes<T> fi(fin_p, Sp);
+        constexpr unsigned SZ = 2 * (unsigned)sizeof(T);  // bytes of a (t, d) pair
         const unsigned bx0 = ln.cx0 * SZ, bxm = ln.cxm * SZ, bxp = ln.cxp * SZ;
         const unsigned own_row = (unsigned)((cz * g.ny + yc) * g.nx);
-        // byte offset of array a (0..2Q-1) at element e within its resource
-        auto soff = [&](int a, unsigned e) { return ((unsigned)(a % kResArrays) * Np + e) * SZ; };
+        // byte offset of direction i's pair at site e within its resource
+        auto soff = [&](int i, unsigned e) { return ((unsigned)(i % kResPairs) * Sp + e) * SZ; };
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             bool bb;
@@ -179,11 +211,9 @@ struct LeanRaw {
             const unsigned col = L::cx[i] > 0 ? bxm : (L::cx[i] < 0 ? bxp : bx0);
             if (W && bb) {
                 const int o = L::opp[i];
-                t[i] = res_load(T(0), fi.r[o / kResArrays], bx0, soff(o, own_row));
-                d[i] = res_load(T(0), fi.r[(Q + o) / kResArrays], bx0, soff(Q + o, own_row));
+                res_load_pair(t[i], d[i], fi.r[o / kResPairs], bx0, soff(o, own_row));
             } else {
-                t[i] = res_load(T(0), fi.r[i / kResArrays], col, soff(i, row));
-                d[i] = res_load(T(0), fi.r[(Q + i) / kResArrays], col, soff(Q + i, row));
+                res_load_pair(t[i], d[i], fi.r[i / kResPairs], col, soff(i, row));
             }
         }
     }
@@ -197,19 +227,19 @@ struct LeanRaw {
         load<W>(g, P.yc, P.cz, ln, t, d);
         if constexpr (W) {
             // lanes next to an x wall: their bounce-backs, from the site itself
-            constexpr unsigned SZ = (unsigned)sizeof(T);
+            constexpr unsigned SZ = 2 * (unsigned)sizeof(T);
             const unsigned bx0 = ln.cx0 * SZ;
-            auto soff = [&](int a, unsigned e) { return ((unsigned)(a % kResArrays) * P.Np + e) * SZ; };
+            const unsigned Sp = P.Np + kRawPad;
+            auto soff = [&](int i, unsigned e) { return ((unsigned)(i % kResPairs) * Sp + e) * SZ; };
             const T* fin_p = fin;
             asm volatile("" : "+s"(fin_p));
-            const PopRes<T> fi(fin_p, P.Np);
+            const PopRes<T> fi(fin_p, Sp);
             if (ln.wall_xlo || ln.wall_xhi) {
 #pragma unroll
                 for (int i = 1; i < Q; ++i) {
                     if (!((L::cx[i] > 0 && ln.wall_xlo) || (L::cx[i] < 0 && ln.wall_xhi))) continue;
                     const int o = L::opp[i];
-                    t[i] = res_load(R(0), fi.r[o / kResArrays], bx0, soff(o, P.own_row));
-                    d[i] = res_load(R(0), fi.r[(Q + o) / kResArrays], bx0, soff(Q + o, P.own_row));
+                    res_load_pair(t[i], d[i], fi.r[o / kResPairs], bx0, soff(o, P.own_row));
                 }
             }
             // moving walls: each reflected direction gains the wall term,
@@ -219,8 +249,10 @@ struct LeanRaw {
             if (g.moving && (wyz || ln.wall_xlo || ln.wall_xhi)) {
                 R st = R(0), sd = R(0);
                 for (int j = 0; j < Q; ++j) {
-                    st += weight<R>(j) + res_load(R(0), fi.r[j / kResArrays], bx0, soff(j, P.own_row));
-                    sd += res_load(R(0), fi.r[(Q + j) / kResArrays], bx0, soff(Q + j, P.own_row));
+                    R tj, dj;
+                    res_load_pair(tj, dj, fi.r[j / kResPairs], bx0, soff(j, P.own_row));
+                    st += weight<R>(j) + tj;
+                    sd += dj;
                 }
                 const R ph = sd / st;
 #pragma unroll
@@ -243,14 +275,12 @@ struct LeanRaw {
         if (site_in) {
             T* fout_p = fout;
             asm volatile("" : "+s"(fout_p));
-            const PopRes<T> fo(fout_p, P.Np);
-            constexpr unsigned SZ = (unsigned)sizeof(T);
-            auto soff = [&](int a, unsigned e) { return ((unsigned)(a % kResArrays) * P.Np + e) * SZ; };
+            const unsigned Sp = P.Np + kRawPad;
+            const PopRes<T> fo(fout_p, Sp);
+            constexpr unsigned SZ = 2 * (unsigned)sizeof(T);
+            auto soff = [&](int i, unsigned e) { return ((unsigned)(i % kResPairs) * Sp + e) * SZ; };
 #pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                res_store(T(t[i]), fo.r[i / kResArrays], ln.cx0 * SZ, soff(i, P.own_row));
-                res_store(T(d[i]), fo.r[(Q + i) / kResArrays], ln.cx0 * SZ, soff(Q + i, P.own_row));
-            }
+            for (int i = 0; i < Q; ++i) res_store_pair(T(t[i]), T(d[i]), fo.r[i / kResPairs], ln.cx0 * SZ, soff(i, P.own_row));
         }
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
@@ -297,7 +327,7 @@ struct LeanSplit {
     }
     __device__ __forceinline__ __amdgpu_buffer_rsrc_t dev_res(const H* p, unsigned N) const {
         asm volatile("" : "+s"(p));
-        return __builtin_amdgcn_make_buffer_rsrc(const_cast<H*>(p), 0, (int)(Q * N * 2u), (int)kRsrcWord3);
+        return __builtin_amdgcn_make_buffer_rsrc(const_cast<H*>(p), 0, (int)(Q * (N + kDevPad) * 2u), (int)kRsrcWord3);
     }
 
     // Loaded one plane ahead, so that their latency overlaps a collision:
@@ -369,7 +399,7 @@ struct LeanSplit {
             const int a = (W && bb) ? L::opp[i] : i;
             const unsigned col = (W && bb) ? ln.cx0 : (L::cx[i] > 0 ? ln.cxm : (L::cx[i] < 0 ? ln.cxp : ln.cx0));
             const unsigned rw = (W && bb) ? own_row : row;
-            pr.dv[i] = __builtin_amdgcn_raw_buffer_load_b16(dr, col * 2u, ((unsigned)a * Np + rw) * 2u, 0);
+            pr.dv[i] = __builtin_amdgcn_raw_buffer_load_b16(dr, col * 2u, ((unsigned)a * (Np + kDevPad) + rw) * 2u, 0);
         }
     }
 
@@ -402,7 +432,7 @@ struct LeanSplit {
                     if (!((L::cx[i] > 0 && ln.wall_xlo) || (L::cx[i] < 0 && ln.wall_xhi))) continue;
                     const int o = L::opp[i];
                     const H dv = __builtin_bit_cast(H, __builtin_amdgcn_raw_buffer_load_b16(
-                                                           dr, ln.cx0 * 2u, ((unsigned)o * P.Np + P.own_row) * 2u, 0));
+                                                           dr, ln.cx0 * 2u, ((unsigned)o * (P.Np + kDevPad) + P.own_row) * 2u, 0));
                     codec.decode(i, o, p0[own], p0[half() + own], dv, t[i], d[i]);
                 }
             }
@@ -447,7 +477,7 @@ struct LeanSplit {
 #pragma unroll
             for (int i = 0; i < Q; ++i)
                 __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, h[i]), dr, ln.cx0 * 2u,
-                                                      ((unsigned)i * P.Np + P.own_row) * 2u, 2);
+                                                      ((unsigned)i * (P.Np + kDevPad) + P.own_row) * 2u, 2);
         }
         (void)g;
 #pragma unroll

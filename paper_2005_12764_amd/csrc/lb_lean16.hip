@@ -8,7 +8,7 @@ template <typename H>
 int launch_lean_split(const LatticeView& v, const SplitPop<H>& src, const SplitPop<H>& dst, const Coeffs<float>& c,
                       const FusedShape& fs) {
     // byte offsets within the record and deviation resources are 32-bit
-    if ((uint64_t)32 * (uint64_t)v.g.N >= ((uint64_t)1 << 32) || (uint64_t)2 * Q * (uint64_t)v.g.N >= ((uint64_t)1 << 32))
+    if ((uint64_t)32 * (uint64_t)v.g.N >= ((uint64_t)1 << 32) || (uint64_t)2 * Q * (uint64_t)dev_stride((size_t)v.g.N) >= ((uint64_t)1 << 32))
         return set_error(LB_EINVAL, "lattice too large for the one-read step of 16-bit storage");
     LeanSplit<H> st;
     st.rin = src.rec;

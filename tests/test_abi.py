@@ -62,12 +62,18 @@ def test_footprint_accounts_for_storage():
     f16 = lb.lb_footprint_bytes(dict(p, storage=W.F16))
     f64 = lb.lb_footprint_bytes(dict(p, storage=W.F64))
     N = 64 ** 3
+    # raw storage: 19 arrays of (t_i, d_i) pairs, each followed by 32 unused
+    # pairs (so that the arrays do not start on a common power-of-two stride)
+    raw_vals = 2 * 19 * (N + 32)
     # two population buffers, the phase field, and the two phase-sum buffers
     # of the one-read step: N own sums plus the x-face sums of the one 64-wide
     # tile column (2 faces x 64 x 64 sites), in pairs, and the phase field of
     # the state; a 16-bit lattice also keeps its raw FP32 initial state
     reals = 2 * (N + 2 * 64 * 64) + N
-    assert f32 == 2 * 2 * 19 * 4 * N + 4 * N + 2 * 4 * reals
-    assert f64 == 2 * 2 * 19 * 8 * N + 8 * N + 2 * 8 * reals
-    assert f16 == 2 * (8 * 4 + 19 * 2) * N + 4 * N + 2 * 4 * reals + 2 * 19 * 4 * N
-    assert lb.lb_footprint_bytes(dict(p, kernel=lb.KERNEL_TWOPASS)) == 2 * 2 * 19 * 4 * N + 4 * N
+    assert f32 == 2 * 4 * raw_vals + 4 * N + 2 * 4 * reals
+    assert f64 == 2 * 8 * raw_vals + 8 * N + 2 * 8 * reals
+    # 16-bit storage: an FP32 record of 8 values per site and 19 arrays of
+    # 16-bit deviations, each followed by 128 unused values
+    split_bytes = 8 * 4 * N + 19 * 2 * (N + 128)
+    assert f16 == 2 * split_bytes + 4 * N + 2 * 4 * reals + 4 * raw_vals
+    assert lb.lb_footprint_bytes(dict(p, kernel=lb.KERNEL_TWOPASS)) == 2 * 4 * raw_vals + 4 * N
