@@ -220,7 +220,9 @@ struct LeanRaw {
     template <bool W>
     __device__ __forceinline__ void dev_load(const Geom&, int, int, const LeanLane&, Pre&) const {}
 
-    template <bool W>
+    // MV: the lattice may have moving walls (resting-wall kernels carry none
+    // of that code)
+    template <bool W, bool MV>
     __device__ __forceinline__ void pull(const Geom& g, const LeanPlane& P, const LeanLane& ln, const Pre&,
                                          R (&t)[Q], R (&d)[Q]) const {
         using L = Lattice;
@@ -246,7 +248,7 @@ struct LeanRaw {
             // shared between the components by the site's own post-collision
             // phase (as RawPop::add_wall_terms)
             const bool wyz = (g.wy && (P.yc == 0 || P.yc == g.ny - 1)) || (g.wz && (P.cz == 0 || P.cz == g.nz - 1));
-            if (g.moving && (wyz || ln.wall_xlo || ln.wall_xhi)) {
+            if (MV && g.moving && (wyz || ln.wall_xlo || ln.wall_xhi)) {
                 R st = R(0), sd = R(0);
                 for (int j = 0; j < Q; ++j) {
                     R tj, dj;
@@ -403,7 +405,7 @@ struct LeanSplit {
         }
     }
 
-    template <bool W>
+    template <bool W, bool MV>
     __device__ __forceinline__ void pull(const Geom& g, const LeanPlane& P, const LeanLane& ln, const Pre& pr,
                                          R (&t)[Q], R (&d)[Q]) const {
         using L = Lattice;
@@ -440,7 +442,7 @@ struct LeanSplit {
             // shared by the phase of the site's own record (as
             // SplitPop::add_wall_terms)
             const bool wyz = (g.wy && (P.yc == 0 || P.yc == g.ny - 1)) || (g.wz && (P.cz == 0 || P.cz == g.nz - 1));
-            if (g.moving && (wyz || ln.wall_xlo || ln.wall_xhi)) {
+            if (MV && g.moving && (wyz || ln.wall_xlo || ln.wall_xhi)) {
                 const float ph = p0[half() + own].x;
 #pragma unroll
                 for (int i = 1; i < Q; ++i) {
@@ -529,7 +531,7 @@ __device__ __forceinline__ void lean_xedge_rows(const Geom& g, const R* __restri
 // planes [za, zb); blockDim.x == 64 * TY.  W: the lattice has walls (an
 // all-periodic lattice carries none of their tests; the lanes next to an x
 // wall take their bounce-backs from a second, masked pull).
-template <typename S, int TY, int H, bool W>
+template <typename S, int TY, int H, bool W, bool MV = false>
 __device__ __forceinline__ void lean_tile(const Geom& g, const S& st, const Coeffs<typename S::R>& cs,
                                           typename S::R* __restrict__ ringb, typename S::R* __restrict__ xch,
                                           Part2<typename S::R>* __restrict__ vs, int x0, int y0, int za, int zb,
@@ -675,7 +677,7 @@ __device__ __forceinline__ void lean_tile(const Geom& g, const S& st, const Coef
         P.rs[2] = (cz + 1 - (za - 1)) % 3;
         // ---- pull (x, y, cz)
         R t[Q], d[Q];
-        st.template pull<W>(g, P, ln, pre, t, d);
+        st.template pull<W, MV>(g, P, ln, pre, t, d);
         st.template dev_load<W>(g, yc, min(cz + 1, g.nz - 1), ln, pre);
         // ---- colour gradient from the ring: base at (ty + H - 1, lane + H - 1)
         R gx, gy, gz;
@@ -724,7 +726,7 @@ __device__ __forceinline__ void lean_tile(const Geom& g, const S& st, const Coef
             const bool zlo = W && g.wz && cz == 0, zhi = W && g.wz && cz == g.nz - 1;
             R ph = R(0);
             bool mv = false;
-            if constexpr (W) {
+            if constexpr (W && MV) {
                 mv = moving_next && (ylo || yhi || zlo || zhi || wall_xlo || wall_xhi);
                 if (mv) {
                     if constexpr (S::split) {
@@ -873,7 +875,7 @@ __host__ __device__ constexpr size_t lean_lds_bytes() {
            (size_t)2 * 3 * TY * sizeof(Part2<R>);
 }
 
-template <typename S, int TY, int H, bool W>
+template <typename S, int TY, int H, bool W, bool MV>
 __global__ __launch_bounds__(kTX * TY) void lean_kernel(Geom g, S st, Coeffs<typename S::R> c, FusedShape fs,
                                                        const Part2<typename S::R>* __restrict__ part_in,
                                                        Part2<typename S::R>* __restrict__ part_out,
@@ -891,7 +893,7 @@ __global__ __launch_bounds__(kTX * TY) void lean_kernel(Geom g, S st, Coeffs<typ
     Part2<R>* vs = reinterpret_cast<Part2<R>*>(lds_raw + off + lean_xch_bytes<R, TY>());
     int x0, y0, za, zb;
     tile_of_block(fs, kTX, g.nz, x0, y0, za, zb);
-    lean_tile<S, TY, H, W>(g, st, c, ringb, xch, vs, x0, y0, za, zb,
+    lean_tile<S, TY, H, W, MV>(g, st, c, ringb, xch, vs, x0, y0, za, zb,
                            phi_of<kTX>(const_cast<Part2<R>*>(part_in), g), part_out, phi_of<kTX>(part_out, g),
                            moving_next);
 }

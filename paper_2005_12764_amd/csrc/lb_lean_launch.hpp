@@ -11,11 +11,11 @@
 namespace lbm {
 namespace lean_launch {
 
-template <typename S, int TY, int HALO, bool W>
+template <typename S, int TY, int HALO, bool W, bool MV>
 int launch_h(const LatticeView& v, const S& st, const Coeffs<typename S::R>& c, const FusedShape& fs) {
     using R = typename S::R;
     const size_t lds = lean_lds_bytes<S, TY, HALO>();
-    auto kern = lean_kernel<S, TY, HALO, W>;
+    auto kern = lean_kernel<S, TY, HALO, W, MV>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -34,8 +34,11 @@ int launch_h(const LatticeView& v, const S& st, const Coeffs<typename S::R>& c, 
 
 template <typename S, int TY, int HALO>
 int launch_w(const LatticeView& v, const S& st, const Coeffs<typename S::R>& c, const FusedShape& fs) {
-    if (v.g.wx || v.g.wy || v.g.wz) return launch_h<S, TY, HALO, true>(v, st, c, fs);
-    return launch_h<S, TY, HALO, false>(v, st, c, fs);
+    // walls at rest and moving walls take separate instantiations (the
+    // resting-wall kernel holds none of the wall-term code)
+    if (v.g.moving || make_geom(*v.p).moving) return launch_h<S, TY, HALO, true, true>(v, st, c, fs);
+    if (v.g.wx || v.g.wy || v.g.wz) return launch_h<S, TY, HALO, true, false>(v, st, c, fs);
+    return launch_h<S, TY, HALO, false, false>(v, st, c, fs);
 }
 
 template <typename S, int TY>
