@@ -377,6 +377,15 @@ def main():
     log("device copy: %.0f GB/s (read + write)" % copy_gbs)
     roof["copy_gbs"] = round(copy_gbs, 1)
     roof["frac_of_copy"] = round(achieved / copy_gbs, 4)
+    if head_name == "f32" and head["kernel"] == 2:
+        # the same kernel's memory access pattern without its arithmetic
+        # (lb_pattern_ms): the ceiling of that pattern on this device
+        from paper_2005_12764_amd import lb
+        pat_ms = lb.lb_pattern_ms(dict(w.params, storage=W.F32), 20)
+        pat_gbs = ALGO_BYTES[st] * w.sites / (pat_ms * 1e-3) / 1e9
+        log("one-read access pattern without arithmetic: %.3f ms, %.0f GB/s" % (pat_ms, pat_gbs))
+        roof["pattern_gbs"] = round(pat_gbs, 1)
+        roof["frac_of_pattern"] = round(achieved / pat_gbs, 4)
 
     kort = None
     if not args.no_korteweg:

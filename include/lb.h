@@ -251,6 +251,20 @@ int lb_set_tiles(int32_t kind, int32_t storage, int32_t ty, int32_t tz);
 /* Bytes of device memory a lattice with these parameters holds. */
 int64_t lb_footprint_bytes(const lb_params* params);
 
+/* Measurement aid for the roofline of the one-read step (not part of the
+ * method): the memory access pattern of the FP32 one-read step on a periodic
+ * lattice of params' sizes, with no arithmetic -- per site the 19 (t_i, d_i)
+ * pair loads at the pull's upstream sites and the 19 pair stores, on that
+ * step's tiles, z chunks, workgroup-to-XCD mapping, two barriers per plane and
+ * LDS allocation (params->storage is ignored; tile settings apply as for an
+ * FP32 lattice).  Allocates two population buffers, runs 2 untimed and `reps`
+ * timed launches on its own stream, frees them, and stores the average launch
+ * duration in milliseconds in *ms.  The rate it gives bounds what the
+ * collide-and-stream kernel can reach with this access pattern on the device.
+ * Errors: LB_EINVAL (params, reps < 1, walls, a lattice the one-read step does
+ * not take, ms NULL), LB_EDEVICE (allocation, launch). */
+int lb_pattern_ms(const lb_params* params, int32_t reps, double* ms);
+
 /* ------------------------------------------------------------------------
  * Batched form: many independent lattices (jobs) of uneven sizes and
  * parameters advanced together: each step is the one-read step of every

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liblb.so")
 
-SOURCES = ["lb_api.hip", "lb_launch.hip", "lb_lean.hip", "lb_lean16.hip", "lb_batch.hip", "lb_noalloc.hip"]
+SOURCES = ["lb_api.hip", "lb_launch.hip", "lb_lean.hip", "lb_lean16.hip", "lb_batch.hip", "lb_noalloc.hip", "lb_pattern.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

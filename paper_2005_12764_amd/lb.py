@@ -116,6 +116,7 @@ def lib():
         "lb_destroy": ([vp], i32),
         "lb_last_error": ([], ctypes.c_char_p),
         "lb_footprint_bytes": ([pp], i64),
+        "lb_pattern_ms": ([pp, i32, dp], i32),
         "lb_batch_create": ([i32, i64, i32, i32, vp, ctypes.POINTER(vp)], i32),
         "lb_batch_add": ([vp, pp, vp, vp, vp, i32, i32, i64, ctypes.POINTER(i32)], i32),
         "lb_batch_add_droplets": ([vp, pp, dp, dp, i32, ctypes.c_double, ctypes.c_double,
@@ -318,6 +319,16 @@ def lb_last_error() -> str:
 def lb_footprint_bytes(params: dict) -> int:
     prm = make_params(params)
     return int(lib().lb_footprint_bytes(ctypes.byref(prm)))
+
+
+def lb_pattern_ms(params: dict, reps: int = 20) -> float:
+    """Average duration (ms) of a launch of the FP32 one-read step's memory
+    access pattern without arithmetic on a periodic lattice of these sizes
+    (lb_pattern_ms)."""
+    prm = make_params(params)
+    out = ctypes.c_double(0.0)
+    _check(lib().lb_pattern_ms(ctypes.byref(prm), int(reps), ctypes.byref(out)))
+    return float(out.value)
 
 
 # ----------------------------------------------------------------------------

@@ -77,3 +77,13 @@ def test_footprint_accounts_for_storage():
     split_bytes = 8 * 4 * N + 19 * 2 * (N + 128)
     assert f16 == 2 * split_bytes + 4 * N + 2 * 4 * reals + 4 * raw_vals
     assert lb.lb_footprint_bytes(dict(p, kernel=lb.KERNEL_TWOPASS)) == 2 * 4 * raw_vals + 4 * N
+
+
+@pytest.mark.parametrize("bad,reps", [(dict(bc=(0, 1, 0)), 5), (dict(), 0), (dict(nx=0), 5)])
+def test_pattern_measurement_rejects_bad_arguments(bad, reps):
+    # rejected before any device call (walls, reps < 1, invalid sizes)
+    p = W.base_params(16, 16, 16, storage=W.F32)
+    p.update(bad)
+    with pytest.raises(lb.LbError) as e:
+        lb.lb_pattern_ms(p, reps)
+    assert e.value.code == lb.LB_EINVAL
