@@ -639,9 +639,10 @@ static int batch_admit(lb_batch_t* b, const lb_params* params, int64_t steps, in
     {
         // 32-bit byte offsets of the tile kernel's buffer resources
         const uint64_t n = (uint64_t)params->nx * params->ny * params->nz;
-        const uint64_t span = b->storage >= LB_STORE_F16 ? 2 * (uint64_t)Q * dev_stride(n) > 32 * n ? 2 * (uint64_t)Q * dev_stride(n) : 32 * n
-                                                         : (uint64_t)kResArrays * (b->storage == LB_STORE_F64 ? 8 : 4) *
-                                                               (uint64_t)raw_stride(n);
+        const uint64_t devs = 2 * (uint64_t)Q * dev_stride(n);
+        const uint64_t span = b->storage >= LB_STORE_F16
+                                  ? (devs > 32 * n ? devs : 32 * n)
+                                  : (uint64_t)kResArrays * (b->storage == LB_STORE_F64 ? 8 : 4) * raw_stride(n);
         if (span >= ((uint64_t)1 << 32)) return bfail(LB_EINVAL, "job too large for the batched step");
     }
     if (steps < 0) return bfail(LB_EINVAL, "steps must be >= 0");

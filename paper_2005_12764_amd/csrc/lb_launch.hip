@@ -374,7 +374,7 @@ int choose_kernel(const lb_params& p) {
     // automatic: the one-read step (measured faster than two passes for raw
     // and 16-bit storage); the Shan-Chen model and lattices too large for
     // 32-bit buffer offsets take two passes
-    // (the one-read step's 32-bit byte offsets need 10 x sites x value size < 2^32)
+    // (the one-read step's 32-bit byte offsets need 10 x raw_stride(sites) x value size < 2^32)
     const bool small =
         (uint64_t)kResArrays * real_size(p) * (uint64_t)raw_stride((size_t)p.nx * p.ny * p.nz) < ((uint64_t)1 << 32);
     if (!fits || !small || p.model != LB_MODEL_COLOUR_GRADIENT) return LB_KERNEL_TWOPASS;

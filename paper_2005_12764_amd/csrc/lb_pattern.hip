@@ -62,8 +62,12 @@ int run(const Geom& g, const FusedShape& fs, size_t lds, const float* a, float* 
                                 (int)lds) != hipSuccess)
             return set_error(LB_EDEVICE, "pattern_kernel LDS");
     }
-    for (int r = 0; r < n; ++r)
-        hipLaunchKernelGGL(kern, dim3(fs.nblocks), dim3(kTX * TY), lds, st, g, (r & 1) ? b : a, (r & 1) ? const_cast<float*>(a) : b, fs, 0.f);
+    // ping-pong: even launches read a and write b, odd ones the reverse
+    for (int r = 0; r < n; ++r) {
+        const float* in = (r & 1) ? b : a;
+        float* out = (r & 1) ? const_cast<float*>(a) : b;
+        hipLaunchKernelGGL(kern, dim3(fs.nblocks), dim3(kTX * TY), lds, st, g, in, out, fs, 0.f);
+    }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return set_error(LB_EDEVICE, (std::string("pattern_kernel: ") + hipGetErrorString(e)).c_str());
     return LB_OK;
