@@ -115,17 +115,22 @@ def copy_bandwidth(stream, gib=2.0, reps=10):
     return 2 * n * 4 / (ms * 1e-3) / 1e9
 
 
-def serving(reqs, prep, rate, steps, budget_gb):
+def serving(reqs, prep, rate, steps, budget_gb, storage="f16"):
+    import copy
     import torch
     from paper_2005_12764_amd import serve as S
     from paper_2005_12764_amd import workloads as W
+    st = {"f32": W.F32, "f16": W.F16, "bf16": W.BF16}[storage]
+    reqs = copy.deepcopy(reqs)
+    for r in reqs:
+        r.params = dict(r.params, storage=st)
     sstream = torch.cuda.Stream()
-    be = S.GpuBackend(int(budget_gb * 2 ** 30), max_jobs=512, storage=W.F16, chunk=50, stream=sstream)
+    be = S.GpuBackend(int(budget_gb * 2 ** 30), max_jobs=512, storage=st, chunk=50, stream=sstream)
     with torch.cuda.stream(sstream):
         rep = S.Server(be, chunk=50).run(reqs)
     be.close()
     out = rep.summary()
-    out.update(storage="f16", rate_jobs_per_s=rate, steps_per_job=steps, budget_gb=budget_gb,
+    out.update(storage=storage, rate_jobs_per_s=rate, steps_per_job=steps, budget_gb=budget_gb,
                request_prep_s=round(prep, 2))
     return out
 
@@ -300,6 +305,9 @@ def main():
                     help="arrival rate of a second serving leg that keeps the batch full "
                          "(its aggregate rate measures the serving form's capacity; 0 = skip)")
     ap.add_argument("--serve-steps", type=int, default=500)
+    ap.add_argument("--serve-sat-storages", default="f32,bf16",
+                    help="other storage forms the batch-kept-full stream also runs in, to set the "
+                         "fp16 serving form beside them on the same jobs ('' = none)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-korteweg", action="store_true", help="skip the Korteweg-diagnostic leg")
     ap.add_argument("--config", default="c2", help="c2 (headline), c3 (crystal channel), c4 (spinodal)")
@@ -393,12 +401,17 @@ def main():
         log("korteweg: %s" % kort)
 
     serve_out = sat_out = None
+    sat_by = {}
     if args.serve_jobs > 0:
         serve_out = serving(reqs, prep, args.serve_rate, args.serve_steps, 0.8 * 288)
         log("serving: %s" % serve_out)
         if sat_reqs is not None:
             sat_out = serving(sat_reqs, prep, args.serve_sat_rate, args.serve_steps, 0.8 * 288)
             log("serving, batch kept full: %s" % sat_out)
+            for name in filter(None, args.serve_sat_storages.split(",")):
+                o = serving(sat_reqs, prep, args.serve_sat_rate, args.serve_steps, 0.8 * 288, storage=name)
+                log("serving, batch kept full, %s storage: %s" % (name, o))
+                sat_by[name] = {k: o[k] for k in ("aggregate_mlups", "device_mlups", "p50_s", "p99_s")}
 
     cpu = None
     if not args.no_cpu:
@@ -436,6 +449,7 @@ def main():
         "korteweg": kort,
         "serving": serve_out,
         "serving_saturated": sat_out,
+        "serving_saturated_other_storage": sat_by or None,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
