@@ -705,7 +705,7 @@ __device__ __forceinline__ void lean_tile(const Geom& g, const S& st, const Coef
             ring_near_contact<R, TX, H>(g, ring, s0, xc, yc, cz, ty + H, lane + H, gx, gy, gz, c, Fx, Fy, Fz);
         }
         SiteTotals<R> tot;
-        collide<R>(t, d, gx, gy, gz, Fx, Fy, Fz, c, &tot);
+        collide<R, S::split>(t, d, gx, gy, gz, Fx, Fy, Fz, c, &tot);
         // ---- store (x, y, cz) and keep the values a later pull reads
         st.store(g, P, ln, t, d, tot, row_in && xin);
         if (ragged) {
